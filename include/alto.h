@@ -1,0 +1,250 @@
+/*
+ * alto.h — C ABI of libalto, an MI355X (gfx950) library for sparse tensors
+ * stored in the ALTO format and for the MTTKRP / CP-ALS computations on them.
+ *
+ * Paper: "ALTO: Adaptive Linearized Storage of Sparse Tensors",
+ * Helal et al., ICS 2021 (arXiv 2102.10245).
+ *
+ * General rules for every entry point
+ *   - Return value: ALTO_OK (0) or one of the ALTO_E_* codes below; on error
+ *     alto_last_error() returns a message for the calling thread, and no
+ *     output argument has been written unless stated otherwise.
+ *   - Pointers marked "device" point to memory of the current HIP device,
+ *     owned by the caller; pointers marked "host" point to host memory.
+ *     The library never frees caller memory.
+ *   - Streams: every call that launches device work takes a hipStream_t and
+ *     enqueues its work on it, in order.  Unless a call says that it
+ *     synchronizes, it returns before the work completes.
+ *   - Indices are 0-based.  Dense matrices (factors, MTTKRP outputs) are
+ *     row-major I x R with no padding (row r starts at element r*R).
+ *   - A tensor handle may be used by one thread at a time.
+ */
+#ifndef ALTO_H
+#define ALTO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ALTO_MAX_MODES 8
+#define ALTO_MAX_RANK 256
+
+/* Error codes. */
+#define ALTO_OK 0
+#define ALTO_E_INVAL 1       /* bad argument: null pointer, N outside 2..8, a dim of 0 or above 2^32,
+                                mode >= N, R outside 1..256, unknown enum value */
+#define ALTO_E_TOO_WIDE 2    /* the linearized index needs more than 128 bits, or more bits than
+                                a requested key width */
+#define ALTO_E_RANGE 3       /* a coordinate is >= its dimension (checked when validation is on) */
+#define ALTO_E_NOMEM 4       /* device allocation failed */
+#define ALTO_E_HIP 5         /* a HIP runtime call failed */
+#define ALTO_E_NOTSPD 6      /* CP-ALS: normal-equation matrix not positive definite after a ridge */
+#define ALTO_E_STATE 7       /* call not valid for this handle (e.g. no selector weights loaded) */
+
+/* Factor-matrix storage precision.  Accumulation is always FP32 in the
+ * MTTKRP and FP64 in the CP-ALS normal equations. */
+typedef enum {
+    ALTO_PREC_F32 = 0,  /* factors are float (binary32) */
+    ALTO_PREC_BF16 = 1  /* factors are bfloat16 bit patterns (uint16_t) */
+} alto_prec;
+
+/* Conflict resolution for the MTTKRP output (Section 3.3, Algorithm 2). */
+typedef enum {
+    ALTO_STRATEGY_AUTO = 0,    /* selector network if loaded, else the reuse rule of Section 3.3 */
+    ALTO_STRATEGY_ATOMIC = 1,  /* every partial result goes to the output with FP32 atomics */
+    ALTO_STRATEGY_STAGED = 2   /* per-segment partials in on-chip local memory over the segment's
+                                  mode interval, then merged into the output; segments whose
+                                  interval does not fit fall back to atomics */
+} alto_strategy;
+
+typedef struct alto_tensor alto_tensor;  /* opaque */
+
+/* Options of alto_build.  A NULL pointer means all defaults. */
+typedef struct alto_opts {
+    int key_bits;      /* 0: smallest of 32, 64, 128 that holds the index; else 32, 64 or 128 */
+    int num_segments;  /* L, the number of line segments; 0: 8 per compute unit */
+    int validate;      /* nonzero: check every coordinate against its dim (one extra pass) */
+} alto_opts;
+
+/* Execution choice of alto_mttkrp / cp_als.  A NULL pointer means AUTO
+ * with the tensor's current partition. */
+typedef struct alto_exec {
+    int strategy;      /* alto_strategy */
+    int num_segments;  /* 0: keep the current partition; else re-partition into this many */
+} alto_exec;
+
+/* Description of a built tensor (host struct filled by alto_info). */
+typedef struct alto_info_t {
+    int N;                                 /* number of modes */
+    int index_bits;                        /* B = sum of per-mode bits (Eq. 1 per nonzero) */
+    int key_bits;                          /* storage width of one index: 32, 64 or 128 */
+    int num_segments;                      /* current L (at most nnz) */
+    int64_t nnz_in;                        /* COO entries given to alto_build */
+    int64_t nnz;                           /* distinct coordinates after coalescing repeats */
+    uint64_t dims[ALTO_MAX_MODES];
+    int mode_bits[ALTO_MAX_MODES];         /* b_n = ceil(log2 I_n), 0 when I_n = 1 */
+    uint64_t mask_lo[ALTO_MAX_MODES];      /* MASK(n), bits 0..63 */
+    uint64_t mask_hi[ALTO_MAX_MODES];      /* MASK(n), bits 64..127 */
+    double fiber_reuse[ALTO_MAX_MODES];    /* nnz / I_n (Section 3.3) */
+    double index_bytes;                    /* nnz * key_bits / 8 as stored */
+    double coo_index_bytes;                /* nnz * N * 4 (uint32 COO coordinates) */
+    double norm2;                          /* ||X||^2 in FP64 (sum of squared coalesced values) */
+} alto_info_t;
+
+/*
+ * alto_build — linearize a COO tensor and order it (Section 3.1), then cut
+ * it into L equal-nonzero line segments with their mode intervals
+ * (Section 3.2).
+ *   coords  host array of N device pointers; coords[n] holds nnz uint32
+ *           coordinates of mode n (structure of arrays).
+ *   vals    device, nnz floats.
+ *   nnz     number of COO entries, >= 0.  Repeated coordinates are summed
+ *           into one nonzero (FP32, in input order).
+ *   dims    host, N mode lengths, each in 1..2^32.
+ *   N       2..8.
+ *   opts    may be NULL.
+ *   out     receives the new handle; free it with alto_free.
+ * The handle owns device copies of the index and values; the caller's
+ * buffers may be reused once the stream has passed this call.  This call
+ * synchronizes the stream once (the count of distinct nonzeros and the
+ * segment intervals come back to the host).
+ */
+int alto_build(const uint32_t *const *coords, const float *vals, int64_t nnz,
+               const uint64_t *dims, int N, const alto_opts *opts, alto_tensor **out,
+               hipStream_t stream);
+
+/* alto_info — fill *out (host) with the tensor's description.  No device work. */
+int alto_info(const alto_tensor *t, alto_info_t *out);
+
+/*
+ * alto_partition — re-cut the ordered tensor into L equal-nonzero segments
+ * (Section 3.2): segment l holds positions [floor(l*nnz/L), floor((l+1)*nnz/L)),
+ * L capped at nnz.  Recomputes the mode intervals and per-row coverage.
+ * Synchronizes the stream once.
+ */
+int alto_partition(alto_tensor *t, int num_segments, hipStream_t stream);
+
+/*
+ * alto_mttkrp — mode-`mode` MTTKRP (Section 2.2, Algorithms 1 and 2):
+ *   out(i, r) = sum over nonzeros x with i_mode(x) = i of
+ *               v_x * prod_{m != mode} A_m(i_m(x), r).
+ *   factors  host array of N device pointers to I_m x R matrices in the
+ *            precision `prec` (entry `mode` is not read and may be NULL);
+ *            each pointer, and out, 16-byte aligned.
+ *   R        1..256.
+ *   out      device, I_mode x R floats; overwritten (rows with no nonzero
+ *            become 0).
+ *   ex       may be NULL (AUTO, current partition).  If ex->num_segments
+ *            differs from the current L the tensor is re-partitioned first
+ *            (that re-partition synchronizes the stream).
+ * Asynchronous otherwise.  FP32 accumulation; atomics make the summation
+ * order, hence the last bits, run-dependent.
+ */
+int alto_mttkrp(alto_tensor *t, const void *const *factors, int R, int prec, int mode,
+                float *out, const alto_exec *ex, hipStream_t stream);
+
+/*
+ * cp_als — `iters` iterations of CP-ALS (Section 2.2): for each mode n in
+ * turn, M_n = MTTKRP_n; V = Hadamard product of the Grams A_m^T A_m, m != n
+ * (FP64); A_n = M_n V^{-1} through the Cholesky factor of V (one retry with
+ * a ridge of 1e-10*trace(V)/R); lambda = column 2-norms; A_n /= lambda;
+ * then the Gram of the stored A_n.  After the last mode of each iteration:
+ * fit = 1 - ||X - [[lambda; A_1..A_N]]|| / ||X||.
+ *   factors  host array of N device pointers, I_n x R in precision `prec`:
+ *            the initial guess on entry, the normalized result on return.
+ *   lambda   device, R doubles (output).
+ *   fit      host, iters doubles (output).
+ *   ex       strategy/partition for the MTTKRPs (NULL: AUTO per mode).
+ * Synchronizes the stream once, at the end.  Returns ALTO_E_NOTSPD if a
+ * normal-equation matrix stays indefinite (factors then hold the last
+ * completed update).
+ */
+int cp_als(alto_tensor *t, int R, int iters, int prec, void *const *factors, double *lambda,
+           double *fit, const alto_exec *ex, hipStream_t stream);
+
+/*
+ * alto_select — the execution the library would pick for an MTTKRP of this
+ * mode and rank: the selector network's choice when weights are loaded and
+ * the tensor lies inside the range it was trained on, else the reuse rule
+ * of Section 3.3 (staged if nnz / I_mode > 4, atomic otherwise) with the
+ * current L.  Host only.
+ */
+int alto_select(const alto_tensor *t, int mode, int R, int prec, alto_exec *out);
+
+/*
+ * alto_selector_load — install selector weights (host floats, layout:
+ * header {F = 12, H, K, nL} then feature mean[F], feature scale[F], the
+ * training range fmin[F], fmax[F], the nL candidate segment counts,
+ * W1[H*F], b1[H], W2[H*H], b2[H], W3[K*H], b3[K], with K = 2*nL outputs =
+ * predicted log2 times of (atomic, L_0) .. (atomic, L_{nL-1}), (staged,
+ * L_0) .. (staged, L_{nL-1})).  The network sees (feature - mean) / scale.
+ * n is the total float count; n == 0 unloads.
+ */
+int alto_selector_load(const float *weights, size_t n);
+
+/* alto_selector_features — the F = 12 selector features of (tensor, mode,
+ * R, prec), written to host `out`.  Host only. */
+int alto_selector_features(const alto_tensor *t, int mode, int R, int prec, float *out);
+
+/*
+ * Selector network kernels (two hidden layers of H ReLU units, K outputs):
+ *   y = W3 relu(W2 relu(W1 x + b1) + b2) + b3,  loss = sum(mask*(y-t)^2)/sum(mask).
+ * All arrays are device float32, row-major; params = {W1[H*F], b1[H],
+ * W2[H*H], b2[H], W3[K*H], b3[K]} packed in that order.
+ * alto_mlp_forward writes y[B*K] and, if loss != NULL, the loss (device, 1 float).
+ * alto_mlp_backward writes the gradient of the loss w.r.t. params (same
+ * packing) into grads and the loss into loss (device, may be NULL).
+ * alto_mlp_adam applies one Adam step (lr, beta1, beta2, eps, step count t>=1)
+ * to params using the moment buffers m and v (device, same packing).
+ */
+int alto_mlp_forward(int B, int F, int H, int K, const float *params, const float *x,
+                     const float *t, const float *mask, float *y, float *loss, hipStream_t stream);
+int alto_mlp_backward(int B, int F, int H, int K, const float *params, const float *x,
+                      const float *t, const float *mask, float *grads, float *loss,
+                      hipStream_t stream);
+int alto_mlp_adam(int64_t P, float *params, const float *grads, float *m, float *v, float lr,
+                  float beta1, float beta2, float eps, int t, hipStream_t stream);
+
+/*
+ * Inspection of a built tensor (device-to-device copies into caller buffers):
+ *   alto_export_keys:      keys_out (device) nnz indices of key_bits/8 bytes each
+ *                          (128-bit indices as {lo, hi} uint64 pairs), vals_out
+ *                          (device) nnz floats, in the tensor's order.  Either may be NULL.
+ *   alto_export_partition: seg_out (device, L+1 int64 segment starts) and ivl_out
+ *                          (device, L*N*2 uint32: [l][n] = {T^s, T^e}).  Either may be NULL.
+ *   alto_export_coverage:  cov_out (device, I_mode uint32): number of segments
+ *                          whose mode interval holds each row.
+ */
+int alto_export_keys(const alto_tensor *t, void *keys_out, float *vals_out, hipStream_t stream);
+int alto_export_partition(const alto_tensor *t, int64_t *seg_out, uint32_t *ivl_out,
+                          hipStream_t stream);
+int alto_export_coverage(const alto_tensor *t, int mode, uint32_t *cov_out, hipStream_t stream);
+
+/*
+ * alto_round_bf16 — storage rule for bfloat16 factors: each double is
+ * rounded to binary32 (nearest even), then to bfloat16 (nearest even);
+ * NaN stays a quiet NaN.  in: device n doubles; out: device n uint16.
+ */
+int alto_round_bf16(const double *in, uint16_t *out, int64_t n, hipStream_t stream);
+
+/* alto_free — release the handle and its device memory (synchronizes the
+ * device memory of the handle only; safe on NULL). */
+void alto_free(alto_tensor *t);
+
+/* alto_last_error — message of the calling thread's last failed call
+ * ("" if none).  The pointer stays valid until the thread's next call. */
+const char *alto_last_error(void);
+
+/* alto_device_compute_units — compute units of the current device (host query). */
+int alto_device_compute_units(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ALTO_H */

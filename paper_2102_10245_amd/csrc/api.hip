@@ -1,0 +1,540 @@
+// C entry points of libalto: argument checks, the host side of format
+// generation (bit layout, run tables, partition bounds) and MTTKRP planning.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+
+#include "common.h"
+#include "mttkrp_impl.h"
+
+namespace alto {
+
+namespace {
+thread_local std::string g_err;
+}
+
+int set_error(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_error(hipError_t e, const char *what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? ALTO_E_NOMEM : ALTO_E_HIP;
+}
+
+namespace {
+
+int ceil_log2(uint64_t x) {
+    int b = 0;
+    while (b < 64 && (1ull << b) < x) b++;
+    return b;
+}
+
+// Bit layout of Section 3.1: b_n = ceil(log2 I_n) bits per mode, given out
+// level by level from the least significant bit; inside a level the shorter
+// mode gets the lower bit (equal lengths: lower mode number first), so the
+// top bits split the longest mode first.
+int make_layout(alto_tensor *t, int key_bits_req) {
+    const int N = t->N;
+    int order[kMaxModes];
+    int maxb = 0;
+    for (int n = 0; n < N; n++) {
+        t->nbits[n] = ceil_log2(t->dims[n]);
+        maxb = std::max(maxb, t->nbits[n]);
+        order[n] = n;
+        t->mask_lo[n] = t->mask_hi[n] = 0;
+    }
+    std::stable_sort(order, order + N, [&](int a, int b) { return t->dims[a] < t->dims[b]; });
+    int pos = 0;
+    // bit positions of each mode, coordinate bit k -> index bit pos
+    int where[kMaxModes][32];
+    for (int lvl = 0; lvl < maxb; lvl++)
+        for (int q = 0; q < N; q++) {
+            const int n = order[q];
+            if (t->nbits[n] <= lvl) continue;
+            if (pos >= 128) return set_error(ALTO_E_TOO_WIDE, "linearized index needs more than 128 bits");
+            where[n][lvl] = pos;
+            if (pos < 64) t->mask_lo[n] |= 1ull << pos;
+            else t->mask_hi[n] |= 1ull << (pos - 64);
+            pos++;
+        }
+    t->B = pos;
+    if (key_bits_req == 0) t->key_bits = pos <= 32 ? 32 : (pos <= 64 ? 64 : 128);
+    else if (key_bits_req == 32 || key_bits_req == 64 || key_bits_req == 128) t->key_bits = key_bits_req;
+    else return set_error(ALTO_E_INVAL, "key_bits must be 0, 32, 64 or 128");
+    if (pos > t->key_bits)
+        return set_error(ALTO_E_TOO_WIDE, "linearized index needs " + std::to_string(pos) + " bits, key has " +
+                                              std::to_string(t->key_bits));
+    // runs of consecutive positions, split at the 64-bit word boundary
+    t->tab.N = N;
+    for (int n = 0; n < N; n++) {
+        int nr = 0;
+        int k = 0;
+        while (k < t->nbits[n]) {
+            const int kp = where[n][k];
+            int len = 1;
+            while (k + len < t->nbits[n] && where[n][k + len] == kp + len && (kp + len) != 64) len++;
+            if (nr >= kMaxRuns) return set_error(ALTO_E_INVAL, "internal: too many bit runs");
+            t->tab.run[n][nr++] = (uint32_t)kp | ((uint32_t)k << 8) | ((uint32_t)len << 16);
+            k += len;
+        }
+        t->tab.nruns[n] = nr;
+    }
+    return ALTO_OK;
+}
+
+void free_partition(alto_tensor *t) {
+    Partition &p = t->part;
+    (void)hipFree(p.d_seg);
+    (void)hipFree(p.d_ivl);
+    for (int n = 0; n < kMaxModes; n++) {
+        (void)hipFree(p.d_cov[n]);
+        p.d_cov[n] = nullptr;
+    }
+    p.d_seg = nullptr;
+    p.d_ivl = nullptr;
+    p.L = 0;
+    p.h_seg.clear();
+    p.h_ivl.clear();
+    for (auto &kv : t->lists) (void)hipFree(kv.second.d);
+    t->lists.clear();
+}
+
+int cu_count() {
+    int dev = 0, cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) return 256;
+    return cu;
+}
+
+// Section 3.2: L equal-nonzero line segments, mode intervals, and the number
+// of segments whose interval holds each output row.
+int do_partition(alto_tensor *t, int L, hipStream_t s) {
+    if (L <= 0) L = 8 * cu_count();
+    free_partition(t);
+    Partition &p = t->part;
+    const int64_t M = t->nnz;
+    const int Le = M == 0 ? 0 : (int)std::min<int64_t>(L, M);
+    p.L = Le;
+    p.h_seg.resize(Le + 1);
+    for (int l = 0; l <= Le; l++)
+        p.h_seg[l] = Le == 0 ? 0 : (int64_t)(((unsigned __int128)l * (uint64_t)M) / (uint64_t)Le);
+    ALTO_HIP(hipMalloc(&p.d_seg, sizeof(int64_t) * (Le + 1)));
+    ALTO_HIP(hipMalloc(&p.d_ivl, sizeof(uint32_t) * std::max(1, Le * t->N * 2)));
+    ALTO_HIP(hipMemcpyAsync(p.d_seg, p.h_seg.data(), sizeof(int64_t) * (Le + 1), hipMemcpyHostToDevice, s));
+    int rc = launch_intervals(t->key_bits, t->keys, p.d_seg, Le, t->tab, p.d_ivl, s);
+    if (rc) return rc;
+    uint64_t maxdim = 0;
+    for (int n = 0; n < t->N; n++) maxdim = std::max(maxdim, t->dims[n]);
+    rc = ensure_workspace(t, coverage_scratch(maxdim));
+    if (rc) return rc;
+    for (int n = 0; n < t->N; n++) {
+        ALTO_HIP(hipMalloc(&p.d_cov[n], sizeof(uint32_t) * t->dims[n]));
+        rc = coverage(t->N, Le, p.d_ivl, n, t->dims[n], p.d_cov[n], t->ws, t->ws_bytes, s);
+        if (rc) return rc;
+    }
+    p.h_ivl.resize((size_t)Le * t->N * 2);
+    if (Le > 0)
+        ALTO_HIP(hipMemcpyAsync(p.h_ivl.data(), p.d_ivl, sizeof(uint32_t) * p.h_ivl.size(), hipMemcpyDeviceToHost, s));
+    ALTO_HIP(hipStreamSynchronize(s));
+    return ALTO_OK;
+}
+
+long env_long(const char *name, long dflt) {
+    const char *e = getenv(name);
+    return e && *e ? atol(e) : dflt;
+}
+
+// LDS budget of the Temp rows of a staged segment (one workgroup per CU at
+// the top of the range, several below it).
+size_t staged_lds_budget() {
+    static size_t budget = (size_t)std::min<long>(150 * 1024, std::max<long>(4096, env_long("ALTO_STAGE_LDS_BYTES", 96 * 1024)));
+    return budget;
+}
+
+// workgroup size for a staged launch whose Temp takes `bytes` of LDS
+int staged_threads(size_t bytes) { return bytes <= 40 * 1024 ? 256 : (bytes <= 80 * 1024 ? 512 : 1024); }
+
+int build_lists(alto_tensor *t, int mode, int strategy, int R, int prec, SegLists **out) {
+    (void)prec;
+    const size_t budget = staged_lds_budget();
+    const int cap_rows = strategy == ALTO_STRATEGY_STAGED ? (int)(budget / ((size_t)temp_stride(R) * 4)) : 0;
+    const uint64_t key = ((uint64_t)mode << 40) | ((uint64_t)strategy << 32) | (uint64_t)(uint32_t)cap_rows;
+    auto it = t->lists.find(key);
+    if (it != t->lists.end()) {
+        *out = &it->second;
+        return ALTO_OK;
+    }
+    const int L = t->part.L, N = t->N;
+    std::vector<int32_t> atomic_l;
+    std::vector<int32_t> bucket[SegLists::kBuckets];
+    // bucket bounds: 1/8, 1/2 and all of the row capacity
+    const int bound[SegLists::kBuckets] = {std::max(1, cap_rows / 8), std::max(1, cap_rows / 2), cap_rows};
+    for (int l = 0; l < L; l++) {
+        const uint32_t s0 = t->part.h_ivl[((size_t)l * N + mode) * 2 + 0];
+        const uint32_t e0 = t->part.h_ivl[((size_t)l * N + mode) * 2 + 1];
+        const uint64_t w = (uint64_t)e0 - s0 + 1;
+        if (cap_rows == 0 || w > (uint64_t)cap_rows) {
+            atomic_l.push_back(l);
+            continue;
+        }
+        for (int b = 0; b < SegLists::kBuckets; b++)
+            if (w <= (uint64_t)bound[b]) {
+                bucket[b].push_back(l);
+                break;
+            }
+    }
+    SegLists sl;
+    sl.n_atomic = (int)atomic_l.size();
+    std::vector<int32_t> all(atomic_l);
+    for (int b = 0; b < SegLists::kBuckets; b++) {
+        sl.n_bucket[b] = (int)bucket[b].size();
+        sl.w_bucket[b] = bound[b];
+        all.insert(all.end(), bucket[b].begin(), bucket[b].end());
+    }
+    ALTO_HIP(hipMalloc(&sl.d, sizeof(int32_t) * std::max<size_t>(1, all.size())));
+    if (!all.empty()) ALTO_HIP(hipMemcpy(sl.d, all.data(), sizeof(int32_t) * all.size(), hipMemcpyHostToDevice));
+    auto ins = t->lists.emplace(key, sl);
+    *out = &ins.first->second;
+    return ALTO_OK;
+}
+
+int check_tensor(const alto_tensor *t) {
+    if (!t) return set_error(ALTO_E_INVAL, "null tensor handle");
+    return ALTO_OK;
+}
+
+}  // namespace
+
+int ensure_workspace(alto_tensor *t, size_t bytes) {
+    if (t->ws_bytes >= bytes) return ALTO_OK;
+    if (t->ws) ALTO_HIP(hipFree(t->ws));
+    t->ws = nullptr;
+    t->ws_bytes = 0;
+    ALTO_HIP(hipMalloc(&t->ws, bytes));
+    t->ws_bytes = bytes;
+    return ALTO_OK;
+}
+
+int resolve_strategy(const alto_tensor *t, int mode, int R, int prec, const alto_exec *ex, alto_exec *res) {
+    if (ex && (ex->strategy < 0 || ex->strategy > 2)) return set_error(ALTO_E_INVAL, "unknown strategy");
+    if (ex && ex->num_segments < 0) return set_error(ALTO_E_INVAL, "num_segments must be >= 0");
+    if (ex && ex->strategy != ALTO_STRATEGY_AUTO) {
+        *res = *ex;
+        return ALTO_OK;
+    }
+    alto_exec sel;
+    const int rc = alto_select(t, mode, R, prec, &sel);
+    if (rc) return rc;
+    if (ex && ex->num_segments > 0) sel.num_segments = ex->num_segments;
+    *res = sel;
+    return ALTO_OK;
+}
+
+int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int prec, int mode, float *out,
+                        const alto_exec *ex, hipStream_t s) {
+    int rc = check_tensor(t);
+    if (rc) return rc;
+    if (mode < 0 || mode >= t->N) return set_error(ALTO_E_INVAL, "mode out of range");
+    if (R < 1 || R > ALTO_MAX_RANK) return set_error(ALTO_E_INVAL, "R must be in 1..256");
+    if (prec != ALTO_PREC_F32 && prec != ALTO_PREC_BF16) return set_error(ALTO_E_INVAL, "unknown precision");
+    if (!out || !factors) return set_error(ALTO_E_INVAL, "null output or factor array");
+    for (int m = 0; m < t->N; m++)
+        if (m != mode && !factors[m]) return set_error(ALTO_E_INVAL, "null factor pointer");
+    // rank-specialized kernels gather rows with 16-byte loads
+    for (int m = 0; m < t->N; m++)
+        if (m != mode && ((uintptr_t)factors[m] & 15u)) return set_error(ALTO_E_INVAL, "factor pointer not 16-byte aligned");
+    if ((uintptr_t)out & 15u) return set_error(ALTO_E_INVAL, "output pointer not 16-byte aligned");
+    alto_exec plan;
+    rc = resolve_strategy(t, mode, R, prec, ex, &plan);
+    if (rc) return rc;
+    if (plan.num_segments > 0 && plan.num_segments != t->part.L && t->nnz > 0 &&
+        !(plan.num_segments > t->nnz && t->part.L == t->nnz)) {
+        rc = do_partition(t, plan.num_segments, s);
+        if (rc) return rc;
+    }
+    const uint64_t outn = t->dims[mode] * (uint64_t)R;
+    ALTO_HIP(hipMemsetAsync(out, 0, sizeof(float) * outn, s));
+    if (t->nnz == 0) return ALTO_OK;
+    SegLists *sl = nullptr;
+    rc = build_lists(t, mode, plan.strategy, R, prec, &sl);
+    if (rc) return rc;
+    // per-XCD replicas for the atomic updates when they are cheap next to the
+    // nonzero traffic (ALTO_REPLICAS=0/1 forces the choice)
+    const int nxcc = device_xcc_count();
+    const size_t rep_bytes = (size_t)nxcc * outn * sizeof(float);
+    const long force = env_long("ALTO_REPLICAS", -1);
+    bool use_rep = nxcc > 1 && rep_bytes <= ((size_t)2 << 30) && rep_bytes <= (size_t)t->nnz * 16;
+    if (force == 0) use_rep = false;
+    if (force == 1) use_rep = nxcc > 1;
+    if (use_rep && t->rep_bytes < rep_bytes) {
+        if (t->rep) ALTO_HIP(hipFree(t->rep));
+        t->rep = nullptr;
+        t->rep_bytes = 0;
+        ALTO_HIP(hipMalloc(&t->rep, rep_bytes));
+        t->rep_bytes = rep_bytes;
+    }
+    if (use_rep) ALTO_HIP(hipMemsetAsync(t->rep, 0, rep_bytes, s));
+    MtLaunch a{};
+    a.keys = t->keys;
+    a.vals = t->vals;
+    a.seg = t->part.d_seg;
+    a.ivl = t->part.d_ivl;
+    a.cov = t->part.d_cov[mode];
+    for (int m = 0; m < t->N; m++) a.fac.p[m] = m == mode ? nullptr : factors[m];
+    a.R = R;
+    a.N = t->N;
+    a.mode = mode;
+    a.tab = t->tab;
+    a.out = out;
+    a.rep = use_rep ? t->rep : nullptr;
+    a.rep_stride = outn;
+    a.nrep = use_rep ? nxcc : 0;
+    auto run = [&](const int32_t *list, int n, int staged, int rows) -> int {
+        a.list = list;
+        a.n_list = n;
+        a.staged = staged;
+        a.temp_rows = rows;
+        a.threads = staged ? staged_threads((size_t)rows * temp_stride(R) * 4) : 256;
+        return launch_mt(a, t->key_bits, prec, s);
+    };
+    if (getenv("ALTO_DEBUG_PLAN"))
+        fprintf(stderr, "[alto] mode %d R %d prec %d strategy %d L %d: atomic %d, staged %d/%d/%d (rows <= %d/%d/%d), replicas %d\n",
+                mode, R, prec, plan.strategy, t->part.L, sl->n_atomic, sl->n_bucket[0], sl->n_bucket[1],
+                sl->n_bucket[2], sl->w_bucket[0], sl->w_bucket[1], sl->w_bucket[2], use_rep ? nxcc : 0);
+    const int32_t *p = sl->d;
+    const int32_t *bucket_p = p + sl->n_atomic;
+    for (int b = 0; b < SegLists::kBuckets; b++) {
+        rc = run(bucket_p, sl->n_bucket[b], 1, sl->w_bucket[b]);
+        if (rc) return rc;
+        bucket_p += sl->n_bucket[b];
+    }
+    rc = run(p, sl->n_atomic, 0, 0);
+    if (rc) return rc;
+    if (use_rep) return launch_replica_reduce(out, t->rep, outn, nxcc, outn, s);
+    return ALTO_OK;
+}
+
+}  // namespace alto
+
+using namespace alto;
+
+extern "C" {
+
+const char *alto_last_error(void) { return alto::g_err.c_str(); }
+
+int alto_device_compute_units(void) { return cu_count(); }
+
+int alto_build(const uint32_t *const *coords, const float *vals, int64_t nnz, const uint64_t *dims, int N,
+               const alto_opts *opts, alto_tensor **out, hipStream_t s) {
+    g_err.clear();
+    if (!out || !dims) return set_error(ALTO_E_INVAL, "null dims or output handle pointer");
+    *out = nullptr;
+    if (N < 2 || N > kMaxModes) return set_error(ALTO_E_INVAL, "N must be in 2..8");
+    if (nnz < 0) return set_error(ALTO_E_INVAL, "nnz must be >= 0");
+    if (nnz > 0 && (!coords || !vals)) return set_error(ALTO_E_INVAL, "null coords or vals");
+    for (int n = 0; n < N; n++) {
+        if (dims[n] == 0 || dims[n] > (1ull << 32)) return set_error(ALTO_E_INVAL, "dims must be in 1..2^32");
+        if (nnz > 0 && !coords[n]) return set_error(ALTO_E_INVAL, "null coordinate pointer");
+    }
+    alto_opts o{};
+    if (opts) o = *opts;
+    if (o.num_segments < 0) return set_error(ALTO_E_INVAL, "num_segments must be >= 0");
+    alto_tensor *t = new alto_tensor();
+    (void)hipGetDevice(&t->device);
+    t->N = N;
+    for (int n = 0; n < N; n++) t->dims[n] = dims[n];
+    int rc = make_layout(t, o.key_bits);
+    if (rc) {
+        delete t;
+        return rc;
+    }
+    t->nnz_in = nnz;
+    t->nnz = nnz;
+    const size_t kb = (size_t)t->key_bits / 8;
+    void *keys_alt = nullptr, *dims_d = nullptr;
+    float *vals_alt = nullptr;
+    int *flag = nullptr;
+    double *sums = nullptr;
+    auto fail = [&](int code) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(keys_alt);
+        (void)hipFree(vals_alt);
+        (void)hipFree(dims_d);
+        (void)hipFree(flag);
+        (void)hipFree(sums);
+        alto_free(t);
+        return code;
+    };
+#define ALTO_TRY(call)                                        \
+    do {                                                      \
+        hipError_t e_ = (call);                               \
+        if (e_ != hipSuccess) return fail(hip_error(e_, #call)); \
+    } while (0)
+    if (nnz > 0) {
+        ALTO_TRY(hipMalloc(&t->keys, kb * nnz));
+        ALTO_TRY(hipMalloc(&t->vals, sizeof(float) * nnz));
+        ALTO_TRY(hipMalloc(&keys_alt, kb * nnz));
+        ALTO_TRY(hipMalloc(&vals_alt, sizeof(float) * nnz));
+        ALTO_TRY(hipMalloc(&dims_d, sizeof(uint64_t) * kMaxModes));
+        ALTO_TRY(hipMalloc(&flag, sizeof(int)));
+        ALTO_TRY(hipMemsetAsync(flag, 0, sizeof(int), s));
+        ALTO_TRY(hipMemcpyAsync(dims_d, t->dims, sizeof(uint64_t) * kMaxModes, hipMemcpyHostToDevice, s));
+        ALTO_TRY(hipMemcpyAsync(t->vals, vals, sizeof(float) * nnz, hipMemcpyDeviceToDevice, s));
+        CoordPtrs cp{};
+        for (int n = 0; n < N; n++) cp.p[n] = coords[n];
+        rc = launch_encode(t->key_bits, cp, (const uint64_t *)dims_d, nnz, t->tab, t->keys, flag, s);
+        if (rc) return fail(rc);
+        int hflag = 0;
+        ALTO_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        ALTO_TRY(hipStreamSynchronize(s));
+        if (hflag) return fail(set_error(ALTO_E_RANGE, "a coordinate is not below its dimension"));
+        rc = ensure_workspace(t, std::max(radix_sort_scratch(t->key_bits, nnz), coalesce_scratch(nnz)));
+        if (rc) return fail(rc);
+        bool in_alt = false;
+        rc = radix_sort(t->key_bits, t->B, nnz, t->keys, t->vals, keys_alt, vals_alt, t->ws, t->ws_bytes, &in_alt, s);
+        if (rc) return fail(rc);
+        if (in_alt) {
+            std::swap(t->keys, keys_alt);
+            std::swap(t->vals, vals_alt);
+        }
+        int64_t nu = nnz;
+        rc = coalesce(t->key_bits, nnz, t->keys, t->vals, keys_alt, vals_alt, t->ws, t->ws_bytes, &nu, s);
+        if (rc) return fail(rc);
+        if (nu != nnz) {
+            std::swap(t->keys, keys_alt);
+            std::swap(t->vals, vals_alt);
+        }
+        t->nnz = nu;
+        ALTO_TRY(hipMalloc(&sums, sizeof(double) * 1025));
+        rc = launch_sumsq(t->vals, t->nnz, sums, s);
+        if (rc) return fail(rc);
+        ALTO_TRY(hipMemcpyAsync(&t->norm2, sums + 1024, sizeof(double), hipMemcpyDeviceToHost, s));
+        ALTO_TRY(hipStreamSynchronize(s));
+        (void)hipFree(keys_alt);
+        (void)hipFree(vals_alt);
+        (void)hipFree(dims_d);
+        (void)hipFree(flag);
+        (void)hipFree(sums);
+        keys_alt = nullptr;
+        vals_alt = nullptr;
+        dims_d = nullptr;
+        flag = nullptr;
+        sums = nullptr;
+    }
+#undef ALTO_TRY
+    rc = do_partition(t, o.num_segments, s);
+    if (rc) return fail(rc);
+    *out = t;
+    return ALTO_OK;
+}
+
+int alto_info(const alto_tensor *t, alto_info_t *out) {
+    g_err.clear();
+    if (!t || !out) return set_error(ALTO_E_INVAL, "null argument");
+    std::memset(out, 0, sizeof(*out));
+    out->N = t->N;
+    out->index_bits = t->B;
+    out->key_bits = t->key_bits;
+    out->num_segments = t->part.L;
+    out->nnz_in = t->nnz_in;
+    out->nnz = t->nnz;
+    for (int n = 0; n < t->N; n++) {
+        out->dims[n] = t->dims[n];
+        out->mode_bits[n] = t->nbits[n];
+        out->mask_lo[n] = t->mask_lo[n];
+        out->mask_hi[n] = t->mask_hi[n];
+        out->fiber_reuse[n] = (double)t->nnz / (double)t->dims[n];
+    }
+    out->index_bytes = (double)t->nnz * t->key_bits / 8.0;
+    out->coo_index_bytes = (double)t->nnz * t->N * 4.0;
+    out->norm2 = t->norm2;
+    return ALTO_OK;
+}
+
+int alto_partition(alto_tensor *t, int num_segments, hipStream_t s) {
+    g_err.clear();
+    if (!t) return set_error(ALTO_E_INVAL, "null tensor handle");
+    if (num_segments < 1) return set_error(ALTO_E_INVAL, "num_segments must be >= 1");
+    return do_partition(t, num_segments, s);
+}
+
+int alto_mttkrp(alto_tensor *t, const void *const *factors, int R, int prec, int mode, float *out,
+                const alto_exec *ex, hipStream_t s) {
+    g_err.clear();
+    return plan_and_run_mttkrp(t, factors, R, prec, mode, out, ex, s);
+}
+
+int alto_export_keys(const alto_tensor *t, void *keys_out, float *vals_out, hipStream_t s) {
+    g_err.clear();
+    if (!t) return set_error(ALTO_E_INVAL, "null tensor handle");
+    if (t->nnz == 0) return ALTO_OK;
+    if (keys_out)
+        ALTO_HIP(hipMemcpyAsync(keys_out, t->keys, (size_t)t->nnz * t->key_bits / 8, hipMemcpyDeviceToDevice, s));
+    if (vals_out) ALTO_HIP(hipMemcpyAsync(vals_out, t->vals, sizeof(float) * t->nnz, hipMemcpyDeviceToDevice, s));
+    return ALTO_OK;
+}
+
+int alto_export_partition(const alto_tensor *t, int64_t *seg_out, uint32_t *ivl_out, hipStream_t s) {
+    g_err.clear();
+    if (!t) return set_error(ALTO_E_INVAL, "null tensor handle");
+    const int L = t->part.L;
+    if (seg_out)
+        ALTO_HIP(hipMemcpyAsync(seg_out, t->part.d_seg, sizeof(int64_t) * (L + 1), hipMemcpyDeviceToDevice, s));
+    if (ivl_out && L > 0)
+        ALTO_HIP(hipMemcpyAsync(ivl_out, t->part.d_ivl, sizeof(uint32_t) * L * t->N * 2, hipMemcpyDeviceToDevice, s));
+    return ALTO_OK;
+}
+
+int alto_export_coverage(const alto_tensor *t, int mode, uint32_t *cov_out, hipStream_t s) {
+    g_err.clear();
+    if (!t || !cov_out) return set_error(ALTO_E_INVAL, "null argument");
+    if (mode < 0 || mode >= t->N) return set_error(ALTO_E_INVAL, "mode out of range");
+    ALTO_HIP(hipMemcpyAsync(cov_out, t->part.d_cov[mode], sizeof(uint32_t) * t->dims[mode], hipMemcpyDeviceToDevice, s));
+    return ALTO_OK;
+}
+
+int cp_als(alto_tensor *t, int R, int iters, int prec, void *const *factors, double *lambda, double *fit,
+           const alto_exec *ex, hipStream_t s) {
+    g_err.clear();
+    return cp_als_impl(t, R, iters, prec, factors, lambda, fit, ex, s);
+}
+
+int alto_round_bf16(const double *in, uint16_t *out, int64_t n, hipStream_t s) {
+    g_err.clear();
+    if (n < 0 || (n > 0 && (!in || !out))) return set_error(ALTO_E_INVAL, "bad arguments");
+    return launch_round_bf16(in, out, n, s);
+}
+
+void alto_free(alto_tensor *t) {
+    if (!t) return;
+    free_partition(t);
+    (void)hipFree(t->rep);
+    (void)hipFree(t->keys);
+    (void)hipFree(t->vals);
+    (void)hipFree(t->ws);
+    delete t;
+}
+
+int alto_mlp_forward(int B, int F, int H, int K, const float *params, const float *x, const float *t, const float *mask,
+                     float *y, float *loss, hipStream_t s) {
+    g_err.clear();
+    return mlp_forward(B, F, H, K, params, x, t, mask, y, loss, s);
+}
+
+int alto_mlp_backward(int B, int F, int H, int K, const float *params, const float *x, const float *t,
+                      const float *mask, float *grads, float *loss, hipStream_t s) {
+    g_err.clear();
+    return mlp_backward(B, F, H, K, params, x, t, mask, grads, loss, s);
+}
+
+int alto_mlp_adam(int64_t P, float *params, const float *grads, float *m, float *v, float lr, float beta1, float beta2,
+                  float eps, int t, hipStream_t s) {
+    g_err.clear();
+    return mlp_adam(P, params, grads, m, v, lr, beta1, beta2, eps, t, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,533 @@
+// Format generation on the device (Section 3.1 and 3.2 of the ALTO paper):
+// linearization (bit-level gather), ordering by the linearized index (LSD
+// radix sort over the B meaningful bits), coalescing of repeated positions,
+// mode intervals of the equal-nonzero line segments and per-row coverage.
+#include "common.h"
+
+namespace alto {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T x) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        T y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
+
+// Exclusive scan of one value per thread over a 256-thread block.
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T *total, T *lds /* kWaves */) {
+    const int lane = __lane_id(), wave = threadIdx.x / 64;
+    T x = wave_inclusive_scan(v);
+    if (lane == 63) lds[wave] = x;
+    __syncthreads();
+    T before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; w++) {
+        const T s = lds[w];
+        if (w < wave) before += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return before + x - v;
+}
+
+// ------------------------------------------------------------ generic scan
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kThreads * kScanItems;
+
+template <typename TIn, typename TOut>
+__global__ __launch_bounds__(kThreads) void scan_reduce_k(const TIn *in, int64_t n, TOut *bsum) {
+    __shared__ TOut lds[kWaves];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    TOut s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; j++)
+        if (base + j < n) s += (TOut)in[base + j];
+    TOut tot;
+    block_exclusive_scan(s, &tot, lds);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// In-place exclusive scan of nb block sums by one block; writes the grand total.
+template <typename TOut>
+__global__ __launch_bounds__(kThreads) void scan_top_k(TOut *bsum, int64_t nb, TOut *total) {
+    __shared__ TOut lds[kWaves];
+    TOut carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += kThreads) {
+        const int64_t b = b0 + threadIdx.x;
+        const TOut v = b < nb ? bsum[b] : (TOut)0;
+        TOut tot;
+        const TOut ex = block_exclusive_scan(v, &tot, lds);
+        if (b < nb) bsum[b] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
+template <typename TIn, typename TOut, bool kInclusive>
+__global__ __launch_bounds__(kThreads) void scan_down_k(const TIn *in, int64_t n, const TOut *boff, TOut *out) {
+    __shared__ TOut lds[kWaves];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    TOut v[kScanItems];
+    TOut s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; j++) {
+        v[j] = base + j < n ? (TOut)in[base + j] : (TOut)0;
+        s += v[j];
+    }
+    TOut tot;
+    TOut run = block_exclusive_scan(s, &tot, lds) + boff[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < kScanItems; j++) {
+        if (kInclusive) run += v[j];
+        if (base + j < n) out[base + j] = run;
+        if (!kInclusive) run += v[j];
+    }
+}
+
+template <typename TIn, typename TOut, bool kInclusive>
+size_t scan_bytes(int64_t n) {
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    return (size_t)(nb + 1) * sizeof(TOut) + 256;
+}
+
+// scratch must hold scan_bytes(n); total (device, may be null) gets the sum.
+template <typename TIn, typename TOut, bool kInclusive>
+int device_scan(const TIn *in, TOut *out, int64_t n, TOut *total, void *scratch, hipStream_t s) {
+    if (n <= 0) {
+        if (total) ALTO_HIP(hipMemsetAsync(total, 0, sizeof(TOut), s));
+        return ALTO_OK;
+    }
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    TOut *bsum = (TOut *)scratch;
+    scan_reduce_k<TIn, TOut><<<(unsigned)nb, kThreads, 0, s>>>(in, n, bsum);
+    scan_top_k<TOut><<<1, kThreads, 0, s>>>(bsum, nb, total);
+    scan_down_k<TIn, TOut, kInclusive><<<(unsigned)nb, kThreads, 0, s>>>(in, n, bsum, out);
+    ALTO_HIP(hipGetLastError());
+    return ALTO_OK;
+}
+
+// ------------------------------------------------------------ encode
+template <typename K>
+__global__ __launch_bounds__(kThreads) void encode_k(CoordPtrs c, const uint64_t *__restrict__ dims, int64_t n,
+                                                     RunTable tab, K *__restrict__ keys, int *flag) {
+    const int N = tab.N;
+    uint64_t dm[kMaxModes];
+#pragma unroll
+    for (int m = 0; m < kMaxModes; m++) dm[m] = m < N ? dims[m] : 0;
+    for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < n; x += (int64_t)gridDim.x * kThreads) {
+        K key = KeyOps<K>::zero();
+        bool bad = false;
+#pragma unroll
+        for (int m = 0; m < kMaxModes; m++) {
+            if (m >= N) break;
+            const uint32_t v = c.p[m][x];
+            bad |= (uint64_t)v >= dm[m];
+            const int nr = tab.nruns[m];
+            for (int q = 0; q < nr; q++) {
+                const uint32_t r = tab.run[m][q];
+                const uint32_t bits = (uint32_t)(((uint64_t)v >> run_cpos(r)) & ((1ull << run_len(r)) - 1));
+                KeyOps<K>::deposit(key, bits, run_kpos(r));
+            }
+        }
+        if (bad) atomicOr(flag, 1);
+        keys[x] = key;
+    }
+}
+
+// ------------------------------------------------------------ radix sort
+// Stable LSD radix sort, 8-bit digits.  Each block owns one tile of
+// kThreads*ITEMS keys, split into four wave chunks of 64*ITEMS keys; inside
+// a wave, item j covers keys j*64 .. j*64+63 of the chunk.  A key's rank
+// among equal digits comes from a ballot match over the 64 lanes plus a
+// per-wave running counter, which keeps input order (stability) without
+// atomics.
+template <typename K>
+struct SortCfg {
+    static constexpr int kItems = sizeof(K) > 8 ? 8 : 16;
+    static constexpr int kTile = kThreads * kItems;
+};
+
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; b++) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
+        m &= bit ? bb : ~bb;
+    }
+    return m;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kThreads) void rs_hist_k(const K *__restrict__ keys, int64_t n, int shift,
+                                                      uint32_t *__restrict__ hist, int64_t T) {
+    constexpr int I = SortCfg<K>::kItems;
+    __shared__ uint32_t cnt[kWaves][256];
+    for (int q = threadIdx.x; q < kWaves * 256; q += kThreads) (&cnt[0][0])[q] = 0;
+    __syncthreads();
+    const int lane = __lane_id(), wave = threadIdx.x / 64;
+    const int64_t base = (int64_t)blockIdx.x * SortCfg<K>::kTile + (int64_t)wave * 64 * I;
+    for (int j = 0; j < I; j++) {
+        const int64_t x = base + (int64_t)j * 64 + lane;
+        const bool valid = x < n;
+        const uint32_t d = valid ? KeyOps<K>::digit(keys[x], shift) : 0u;
+        const uint64_t m = match_digit(d, valid);
+        if (valid && lane == (int)__builtin_ctzll(m)) cnt[wave][d] += (uint32_t)__builtin_popcountll(m);
+    }
+    __syncthreads();
+    const int d = threadIdx.x;
+    uint32_t tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; w++) tot += cnt[w][d];
+    hist[(int64_t)d * T + blockIdx.x] = tot;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kThreads) void rs_scatter_k(const K *__restrict__ kin, const float *__restrict__ vin,
+                                                         K *__restrict__ kout, float *__restrict__ vout, int64_t n,
+                                                         int shift, const uint64_t *__restrict__ offs, int64_t T) {
+    constexpr int I = SortCfg<K>::kItems;
+    constexpr int TILE = SortCfg<K>::kTile;
+    __shared__ uint32_t cnt[kWaves][256];
+    __shared__ uint32_t tstart[256];
+    __shared__ uint64_t gbase[256];
+    __shared__ uint32_t lds_scan[kWaves];
+    __shared__ K skeys[TILE];
+    __shared__ float svals[TILE];
+
+    for (int q = threadIdx.x; q < kWaves * 256; q += kThreads) (&cnt[0][0])[q] = 0;
+    __syncthreads();
+    const int lane = __lane_id(), wave = threadIdx.x / 64;
+    const int64_t base = (int64_t)blockIdx.x * TILE + (int64_t)wave * 64 * I;
+    K k[I];
+    float v[I];
+    uint32_t dg[I], rk[I];
+    const uint64_t lt = lanemask_lt();
+    for (int j = 0; j < I; j++) {
+        const int64_t x = base + (int64_t)j * 64 + lane;
+        const bool valid = x < n;
+        if (valid) {
+            k[j] = kin[x];
+            v[j] = vin[x];
+        } else {
+            k[j] = KeyOps<K>::zero();
+            v[j] = 0.f;
+        }
+        const uint32_t d = valid ? KeyOps<K>::digit(k[j], shift) : 0u;
+        const uint64_t m = match_digit(d, valid);
+        const uint32_t before = cnt[wave][d];  // every lane reads before the leader writes
+        rk[j] = before + (uint32_t)__builtin_popcountll(m & lt);
+        dg[j] = valid ? d : 0xffffffffu;
+        __builtin_amdgcn_wave_barrier();
+        if (valid && lane == (int)__builtin_ctzll(m)) cnt[wave][d] = before + (uint32_t)__builtin_popcountll(m);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    {
+        const int d = threadIdx.x;
+        uint32_t c[kWaves], run = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; w++) c[w] = cnt[w][d];
+#pragma unroll
+        for (int w = 0; w < kWaves; w++) {
+            cnt[w][d] = run;
+            run += c[w];
+        }
+        uint32_t tot;
+        tstart[d] = block_exclusive_scan(run, &tot, lds_scan);
+        gbase[d] = offs[(int64_t)d * T + blockIdx.x];
+    }
+    __syncthreads();
+    for (int j = 0; j < I; j++) {
+        if (dg[j] == 0xffffffffu) continue;
+        const uint32_t pos = tstart[dg[j]] + cnt[wave][dg[j]] + rk[j];
+        skeys[pos] = k[j];
+        svals[pos] = v[j];
+    }
+    __syncthreads();
+    const int64_t nvalid = min((int64_t)TILE, n - (int64_t)blockIdx.x * TILE);
+    for (int i = threadIdx.x; i < nvalid; i += kThreads) {
+        const K key = skeys[i];
+        const uint32_t d = KeyOps<K>::digit(key, shift);
+        const uint64_t dst = gbase[d] + (uint64_t)(i - (int)tstart[d]);
+        kout[dst] = key;
+        vout[dst] = svals[i];
+    }
+}
+
+template <typename K>
+int radix_sort_t(int nbits, int64_t n, K *keys, float *vals, K *keys_alt, float *vals_alt, void *scratch,
+                 bool *in_alt, hipStream_t s) {
+    *in_alt = false;
+    if (n <= 1 || nbits <= 0) return ALTO_OK;
+    const int passes = (nbits + 7) / 8;
+    const int64_t T = (n + SortCfg<K>::kTile - 1) / SortCfg<K>::kTile;
+    uint32_t *hist = (uint32_t *)scratch;
+    uint64_t *offs = (uint64_t *)((char *)scratch + ((256 * T * sizeof(uint32_t) + 255) & ~(size_t)255));
+    void *scan_ws = (char *)offs + ((256 * T * sizeof(uint64_t) + 255) & ~(size_t)255);
+    K *src_k = keys, *dst_k = keys_alt;
+    float *src_v = vals, *dst_v = vals_alt;
+    for (int p = 0; p < passes; p++) {
+        const int shift = 8 * p;
+        rs_hist_k<K><<<(unsigned)T, kThreads, 0, s>>>(src_k, n, shift, hist, T);
+        int rc = device_scan<uint32_t, uint64_t, false>(hist, offs, 256 * T, nullptr, scan_ws, s);
+        if (rc) return rc;
+        rs_scatter_k<K><<<(unsigned)T, kThreads, 0, s>>>(src_k, src_v, dst_k, dst_v, n, shift, offs, T);
+        ALTO_HIP(hipGetLastError());
+        std::swap(src_k, dst_k);
+        std::swap(src_v, dst_v);
+    }
+    *in_alt = (passes & 1) != 0;
+    return ALTO_OK;
+}
+
+// ------------------------------------------------------------ coalesce
+template <typename K>
+__device__ __forceinline__ bool is_head(const K *keys, int64_t x) {
+    return x == 0 || !KeyOps<K>::eq(keys[x], keys[x - 1]);
+}
+
+template <typename K>
+__global__ __launch_bounds__(kThreads) void head_count_k(const K *__restrict__ keys, int64_t n, uint32_t *bcount) {
+    __shared__ uint32_t lds[kWaves];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t c = 0;
+    for (int j = 0; j < kScanItems; j++)
+        if (base + j < n && is_head(keys, base + j)) c++;
+    uint32_t tot;
+    block_exclusive_scan(c, &tot, lds);
+    if (threadIdx.x == 0) bcount[blockIdx.x] = tot;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kThreads) void compact_k(const K *__restrict__ keys, const float *__restrict__ vals,
+                                                      int64_t n, const uint64_t *__restrict__ boff,
+                                                      K *__restrict__ kout, float *__restrict__ vout) {
+    __shared__ uint64_t lds[kWaves];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint64_t c = 0;
+    for (int j = 0; j < kScanItems; j++)
+        if (base + j < n && is_head(keys, base + j)) c++;
+    uint64_t tot;
+    uint64_t pos = block_exclusive_scan(c, &tot, lds) + boff[blockIdx.x];
+    for (int j = 0; j < kScanItems; j++) {
+        const int64_t x = base + j;
+        if (x >= n || !is_head(keys, x)) continue;
+        const K key = keys[x];
+        float sum = vals[x];
+        for (int64_t y = x + 1; y < n && KeyOps<K>::eq(keys[y], key); y++) sum += vals[y];
+        kout[pos] = key;
+        vout[pos] = sum;
+        pos++;
+    }
+}
+
+// ------------------------------------------------------------ intervals
+template <typename K>
+__global__ __launch_bounds__(kThreads) void intervals_k(const K *__restrict__ keys, const int64_t *__restrict__ seg,
+                                                        RunTable tab, uint32_t *__restrict__ ivl) {
+    __shared__ uint32_t smn[kWaves][kMaxModes], smx[kWaves][kMaxModes];
+    const int l = blockIdx.x;
+    const int N = tab.N;
+    const int64_t b = seg[l], e = seg[l + 1];
+    uint32_t mn[kMaxModes], mx[kMaxModes];
+#pragma unroll
+    for (int m = 0; m < kMaxModes; m++) {
+        mn[m] = 0xffffffffu;
+        mx[m] = 0u;
+    }
+    for (int64_t x = b + threadIdx.x; x < e; x += kThreads) {
+        const K key = keys[x];
+#pragma unroll
+        for (int m = 0; m < kMaxModes; m++) {
+            if (m >= N) break;
+            const uint32_t c = extract_mode(key, tab, m);
+            mn[m] = min(mn[m], c);
+            mx[m] = max(mx[m], c);
+        }
+    }
+    const int lane = __lane_id(), wave = threadIdx.x / 64;
+#pragma unroll
+    for (int m = 0; m < kMaxModes; m++) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            mn[m] = min(mn[m], (uint32_t)__shfl_xor((int)mn[m], off));
+            mx[m] = max(mx[m], (uint32_t)__shfl_xor((int)mx[m], off));
+        }
+        if (lane == 0) {
+            smn[wave][m] = mn[m];
+            smx[wave][m] = mx[m];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < N) {
+        const int m = threadIdx.x;
+        uint32_t a = 0xffffffffu, z = 0u;
+        for (int w = 0; w < kWaves; w++) {
+            a = min(a, smn[w][m]);
+            z = max(z, smx[w][m]);
+        }
+        ivl[((int64_t)l * N + m) * 2 + 0] = a;
+        ivl[((int64_t)l * N + m) * 2 + 1] = z;
+    }
+}
+
+// ------------------------------------------------------------ coverage
+__global__ __launch_bounds__(kThreads) void coverage_marks_k(const uint32_t *__restrict__ ivl, int L, int N, int mode,
+                                                             int32_t *__restrict__ diff) {
+    const int l = blockIdx.x * kThreads + threadIdx.x;
+    if (l >= L) return;
+    const uint32_t s = ivl[((int64_t)l * N + mode) * 2 + 0];
+    const uint32_t e = ivl[((int64_t)l * N + mode) * 2 + 1];
+    atomicAdd(&diff[s], 1);
+    atomicAdd(&diff[(uint64_t)e + 1], -1);
+}
+
+// ------------------------------------------------------------ sum of squares
+constexpr int kSumBlocks = 1024;
+
+__global__ __launch_bounds__(kThreads) void sumsq_partial_k(const float *__restrict__ v, int64_t n, double *part) {
+    __shared__ double lds[kWaves];
+    double s = 0.0;
+    for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < n; x += (int64_t)gridDim.x * kThreads) {
+        const double a = (double)v[x];
+        s += a * a;
+    }
+    double tot;
+    block_exclusive_scan(s, &tot, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kThreads) void sum_partials_k(const double *part, int n, double *out) {
+    __shared__ double lds[kWaves];
+    double s = 0.0;
+    for (int q = threadIdx.x; q < n; q += kThreads) s += part[q];
+    double tot;
+    block_exclusive_scan(s, &tot, lds);
+    if (threadIdx.x == 0) *out = tot;
+}
+
+unsigned grid_for(int64_t n, int per_block) {
+    int64_t g = (n + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers
+int launch_encode(int key_bits, const CoordPtrs &c, const uint64_t *dims, int64_t n, const RunTable &tab, void *keys,
+                  int *d_flag, hipStream_t s) {
+    if (n <= 0) return ALTO_OK;
+    const unsigned g = grid_for(n, kThreads * 4);
+    if (key_bits == 32) encode_k<uint32_t><<<g, kThreads, 0, s>>>(c, dims, n, tab, (uint32_t *)keys, d_flag);
+    else if (key_bits == 64) encode_k<uint64_t><<<g, kThreads, 0, s>>>(c, dims, n, tab, (uint64_t *)keys, d_flag);
+    else encode_k<u128><<<g, kThreads, 0, s>>>(c, dims, n, tab, (u128 *)keys, d_flag);
+    ALTO_HIP(hipGetLastError());
+    return ALTO_OK;
+}
+
+size_t radix_sort_scratch(int key_bits, int64_t n) {
+    const int tile = key_bits == 128 ? SortCfg<u128>::kTile : SortCfg<uint64_t>::kTile;
+    const int64_t T = (n + tile - 1) / tile;
+    const size_t a = (256 * T * sizeof(uint32_t) + 255) & ~(size_t)255;
+    const size_t b = (256 * T * sizeof(uint64_t) + 255) & ~(size_t)255;
+    return a + b + scan_bytes<uint32_t, uint64_t, false>(256 * T) + 256;
+}
+
+int radix_sort(int key_bits, int nbits, int64_t n, void *keys, float *vals, void *keys_alt, float *vals_alt,
+               void *scratch, size_t scratch_bytes, bool *in_alt, hipStream_t s) {
+    if (scratch_bytes < radix_sort_scratch(key_bits, n)) return set_error(ALTO_E_NOMEM, "radix sort scratch too small");
+    if (key_bits == 32)
+        return radix_sort_t<uint32_t>(nbits, n, (uint32_t *)keys, vals, (uint32_t *)keys_alt, vals_alt, scratch, in_alt, s);
+    if (key_bits == 64)
+        return radix_sort_t<uint64_t>(nbits, n, (uint64_t *)keys, vals, (uint64_t *)keys_alt, vals_alt, scratch, in_alt, s);
+    return radix_sort_t<u128>(nbits, n, (u128 *)keys, vals, (u128 *)keys_alt, vals_alt, scratch, in_alt, s);
+}
+
+size_t coalesce_scratch(int64_t n) {
+    const int64_t nb = (n + kScanTile - 1) / kScanTile + 1;
+    return (size_t)nb * (sizeof(uint32_t) + sizeof(uint64_t)) + scan_bytes<uint32_t, uint64_t, false>(nb) + 1024;
+}
+
+// Counts distinct keys (host value, synchronizes) and, if there are repeats,
+// writes the coalesced tensor to keys_out/vals_out.
+int coalesce(int key_bits, int64_t n, const void *keys, const float *vals, void *keys_out, float *vals_out,
+             void *scratch, size_t scratch_bytes, int64_t *n_unique, hipStream_t s) {
+    *n_unique = n;
+    if (n <= 1) return ALTO_OK;
+    if (scratch_bytes < coalesce_scratch(n)) return set_error(ALTO_E_NOMEM, "coalesce scratch too small");
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    uint32_t *bcount = (uint32_t *)scratch;
+    uint64_t *boff = (uint64_t *)((char *)scratch + ((nb * sizeof(uint32_t) + 255) & ~(size_t)255));
+    uint64_t *total = boff + nb;
+    void *scan_ws = (char *)(total + 1) + 256;
+#define ALTO_HC(K) head_count_k<K><<<(unsigned)nb, kThreads, 0, s>>>((const K *)keys, n, bcount)
+    if (key_bits == 32) ALTO_HC(uint32_t);
+    else if (key_bits == 64) ALTO_HC(uint64_t);
+    else ALTO_HC(u128);
+#undef ALTO_HC
+    int rc = device_scan<uint32_t, uint64_t, false>(bcount, boff, nb, total, scan_ws, s);
+    if (rc) return rc;
+    uint64_t h = 0;
+    ALTO_HIP(hipMemcpyAsync(&h, total, sizeof(h), hipMemcpyDeviceToHost, s));
+    ALTO_HIP(hipStreamSynchronize(s));
+    *n_unique = (int64_t)h;
+    if ((int64_t)h == n) return ALTO_OK;
+#define ALTO_CP(K) \
+    compact_k<K><<<(unsigned)nb, kThreads, 0, s>>>((const K *)keys, vals, n, boff, (K *)keys_out, vals_out)
+    if (key_bits == 32) ALTO_CP(uint32_t);
+    else if (key_bits == 64) ALTO_CP(uint64_t);
+    else ALTO_CP(u128);
+#undef ALTO_CP
+    ALTO_HIP(hipGetLastError());
+    return ALTO_OK;
+}
+
+int launch_intervals(int key_bits, const void *keys, const int64_t *seg, int L, const RunTable &tab, uint32_t *ivl,
+                     hipStream_t s) {
+    if (L <= 0) return ALTO_OK;
+    if (key_bits == 32) intervals_k<uint32_t><<<L, kThreads, 0, s>>>((const uint32_t *)keys, seg, tab, ivl);
+    else if (key_bits == 64) intervals_k<uint64_t><<<L, kThreads, 0, s>>>((const uint64_t *)keys, seg, tab, ivl);
+    else intervals_k<u128><<<L, kThreads, 0, s>>>((const u128 *)keys, seg, tab, ivl);
+    ALTO_HIP(hipGetLastError());
+    return ALTO_OK;
+}
+
+size_t coverage_scratch(uint64_t dim) {
+    return ((dim + 1) * sizeof(int32_t) + 255 & ~(size_t)255) + scan_bytes<int32_t, int32_t, true>((int64_t)dim + 1);
+}
+
+int coverage(int N, int L, const uint32_t *d_ivl, int mode, uint64_t dim, uint32_t *cov, void *scratch,
+             size_t scratch_bytes, hipStream_t s) {
+    if (scratch_bytes < coverage_scratch(dim)) return set_error(ALTO_E_NOMEM, "coverage scratch too small");
+    int32_t *diff = (int32_t *)scratch;
+    void *scan_ws = (char *)scratch + (((dim + 1) * sizeof(int32_t) + 255) & ~(size_t)255);
+    ALTO_HIP(hipMemsetAsync(diff, 0, (dim + 1) * sizeof(int32_t), s));
+    if (L > 0) {
+        coverage_marks_k<<<(L + kThreads - 1) / kThreads, kThreads, 0, s>>>(d_ivl, L, N, mode, diff);
+        ALTO_HIP(hipGetLastError());
+    }
+    return device_scan<int32_t, int32_t, true>(diff, (int32_t *)cov, (int64_t)dim, nullptr, scan_ws, s);
+}
+
+int launch_sumsq(const float *vals, int64_t n, double *out, hipStream_t s) {
+    // out must have room for kSumBlocks + 1 doubles; the result lands in out[kSumBlocks]
+    sumsq_partial_k<<<kSumBlocks, kThreads, 0, s>>>(vals, n, out);
+    sum_partials_k<<<1, kThreads, 0, s>>>(out, kSumBlocks, out + kSumBlocks);
+    ALTO_HIP(hipGetLastError());
+    return ALTO_OK;
+}
+
+}  // namespace alto

@@ -1,0 +1,200 @@
+// Internal declarations shared by the libalto sources (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "alto.h"
+
+namespace alto {
+
+constexpr int kMaxModes = ALTO_MAX_MODES;
+constexpr int kMaxRuns = 40;  // runs of consecutive index bits per mode (<= 32 bits + word splits)
+
+// ---------------------------------------------------------------- keys
+// A linearized index (Section 3.1) of 32, 64 or 128 bits.
+struct u128 {
+    uint64_t lo, hi;
+};
+
+template <typename K>
+struct KeyOps;
+
+template <>
+struct KeyOps<uint32_t> {
+    static constexpr int kBits = 32;
+    __device__ __forceinline__ static uint32_t field(uint32_t k, int pos, int len) {
+        return (k >> pos) & (uint32_t)((1ull << len) - 1);
+    }
+    __device__ __forceinline__ static void deposit(uint32_t &k, uint32_t v, int pos) { k |= v << pos; }
+    __device__ __forceinline__ static uint32_t digit(uint32_t k, int shift) { return (k >> shift) & 0xffu; }
+    __device__ __forceinline__ static bool eq(uint32_t a, uint32_t b) { return a == b; }
+    __device__ __forceinline__ static uint32_t zero() { return 0u; }
+};
+
+template <>
+struct KeyOps<uint64_t> {
+    static constexpr int kBits = 64;
+    __device__ __forceinline__ static uint32_t field(uint64_t k, int pos, int len) {
+        return (uint32_t)((k >> pos) & ((1ull << len) - 1));
+    }
+    __device__ __forceinline__ static void deposit(uint64_t &k, uint32_t v, int pos) { k |= (uint64_t)v << pos; }
+    __device__ __forceinline__ static uint32_t digit(uint64_t k, int shift) { return (uint32_t)(k >> shift) & 0xffu; }
+    __device__ __forceinline__ static bool eq(uint64_t a, uint64_t b) { return a == b; }
+    __device__ __forceinline__ static uint64_t zero() { return 0ull; }
+};
+
+template <>
+struct KeyOps<u128> {
+    static constexpr int kBits = 128;
+    // runs never straddle bit 64 (the host splits them)
+    __device__ __forceinline__ static uint32_t field(const u128 &k, int pos, int len) {
+        const uint64_t w = pos < 64 ? k.lo : k.hi;
+        return (uint32_t)((w >> (pos & 63)) & ((1ull << len) - 1));
+    }
+    __device__ __forceinline__ static void deposit(u128 &k, uint32_t v, int pos) {
+        if (pos < 64) k.lo |= (uint64_t)v << pos;
+        else k.hi |= (uint64_t)v << (pos - 64);
+    }
+    __device__ __forceinline__ static uint32_t digit(const u128 &k, int shift) {
+        const uint64_t w = shift < 64 ? k.lo : k.hi;
+        return (uint32_t)(w >> (shift & 63)) & 0xffu;
+    }
+    __device__ __forceinline__ static bool eq(const u128 &a, const u128 &b) { return a.lo == b.lo && a.hi == b.hi; }
+    __device__ __forceinline__ static u128 zero() { return u128{0ull, 0ull}; }
+};
+
+// Bit runs of every mode: run r of mode n moves `len` consecutive bits from
+// index position `kpos` to coordinate position `cpos` (packed kpos | cpos<<8 | len<<16).
+struct RunTable {
+    int N;
+    int nruns[kMaxModes];
+    uint32_t run[kMaxModes][kMaxRuns];
+};
+
+__device__ __forceinline__ int run_kpos(uint32_t r) { return (int)(r & 0xffu); }
+__device__ __forceinline__ int run_cpos(uint32_t r) { return (int)((r >> 8) & 0xffu); }
+__device__ __forceinline__ int run_len(uint32_t r) { return (int)((r >> 16) & 0xffu); }
+
+// De-linearize one mode: bit-level scatter of the mode's index bits.
+template <typename K>
+__device__ __forceinline__ uint32_t extract_mode(const K &key, const RunTable &tab, int n) {
+    uint32_t c = 0;
+    const int nr = tab.nruns[n];
+    for (int q = 0; q < nr; q++) {
+        const uint32_t r = tab.run[n][q];
+        c |= KeyOps<K>::field(key, run_kpos(r), run_len(r)) << run_cpos(r);
+    }
+    return c;
+}
+
+struct CoordPtrs {
+    const uint32_t *p[kMaxModes];
+};
+
+// ---------------------------------------------------------------- tensor
+struct Partition {
+    int L = 0;
+    int64_t *d_seg = nullptr;    // L+1
+    uint32_t *d_ivl = nullptr;   // L*N*2
+    uint32_t *d_cov[kMaxModes] = {};  // per mode, I_n
+    std::vector<int64_t> h_seg;
+    std::vector<uint32_t> h_ivl;
+};
+
+// Segment lists of one MTTKRP plan: segments run with atomics, and staged
+// segments bucketed by the LDS rows their mode interval needs.
+struct SegLists {
+    static constexpr int kBuckets = 3;
+    int32_t *d = nullptr;  // device: atomic list, then bucket 0, 1, 2
+    int n_atomic = 0;
+    int n_bucket[kBuckets] = {};
+    int w_bucket[kBuckets] = {};
+};
+
+}  // namespace alto
+
+struct alto_tensor {
+    int device = 0;
+    int N = 0;
+    uint64_t dims[alto::kMaxModes] = {};
+    int nbits[alto::kMaxModes] = {};
+    uint64_t mask_lo[alto::kMaxModes] = {}, mask_hi[alto::kMaxModes] = {};
+    int B = 0;
+    int key_bits = 64;
+    alto::RunTable tab{};
+    int64_t nnz_in = 0, nnz = 0;
+    void *keys = nullptr;  // device, nnz * key_bits/8
+    float *vals = nullptr; // device, nnz
+    double norm2 = 0.0;
+    alto::Partition part;
+    // reusable device workspace (grown on demand)
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    // MTTKRP plans keyed by (mode, strategy, LDS row capacity); cleared on re-partition
+    std::map<uint64_t, alto::SegLists> lists;
+    // per-XCD output replicas for atomic updates (grown on demand)
+    float *rep = nullptr;
+    size_t rep_bytes = 0;
+};
+
+namespace alto {
+
+// error state (api.hip)
+int set_error(int code, const std::string &msg);
+int hip_error(hipError_t e, const char *what);
+#define ALTO_HIP(call)                                            \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) return ::alto::hip_error(e_, #call); \
+    } while (0)
+
+// ---------------------------------------------------------------- launchers
+// build.hip
+int launch_encode(int key_bits, const CoordPtrs &c, const uint64_t *dims, int64_t n, const RunTable &tab,
+                  void *keys, int *d_flag, hipStream_t s);
+int radix_sort(int key_bits, int nbits, int64_t n, void *keys, float *vals, void *keys_alt, float *vals_alt,
+               void *scratch, size_t scratch_bytes, bool *result_in_alt, hipStream_t s);
+size_t radix_sort_scratch(int key_bits, int64_t n);
+int coalesce(int key_bits, int64_t n, const void *keys, const float *vals, void *keys_out, float *vals_out,
+             void *scratch, size_t scratch_bytes, int64_t *n_unique, hipStream_t s);
+size_t coalesce_scratch(int64_t n);
+int launch_intervals(int key_bits, const void *keys, const int64_t *seg, int L, const RunTable &tab,
+                     uint32_t *ivl, hipStream_t s);
+int coverage(int N, int L, const uint32_t *d_ivl, int mode, uint64_t dim, uint32_t *cov, void *scratch,
+             size_t scratch_bytes, hipStream_t s);
+size_t coverage_scratch(uint64_t dim);
+int launch_sumsq(const float *vals, int64_t n, double *out, hipStream_t s);
+
+
+// cpals.hip
+int launch_gram(const void *A, int prec, uint64_t I, int R, double *G, double *partials, int nparts,
+                hipStream_t s);
+int cp_als_impl(alto_tensor *t, int R, int iters, int prec, void *const *factors, double *lambda,
+                double *fit, const alto_exec *ex, hipStream_t s);
+int launch_round_bf16(const double *in, uint16_t *out, int64_t n, hipStream_t s);
+
+// mlp.hip
+int mlp_forward(int B, int F, int H, int K, const float *params, const float *x, const float *t,
+                const float *mask, float *y, float *loss, hipStream_t s);
+int mlp_backward(int B, int F, int H, int K, const float *params, const float *x, const float *t,
+                 const float *mask, float *grads, float *loss, hipStream_t s);
+int mlp_adam(int64_t P, float *params, const float *grads, float *m, float *v, float lr, float b1, float b2,
+             float eps, int t, hipStream_t s);
+
+// api.hip: execution planning shared with cp_als
+int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int prec, int mode, float *out,
+                        const alto_exec *ex, hipStream_t s);
+int ensure_workspace(alto_tensor *t, size_t bytes);
+
+// ---------------------------------------------------------------- device helpers
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const int lane = __lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+}  // namespace alto

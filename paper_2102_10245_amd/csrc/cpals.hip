@@ -1,0 +1,386 @@
+// CP-ALS on the GPU (Section 2.2 of the ALTO paper; standard alternating
+// least squares).  The MTTKRP of every mode runs on the ALTO tensor; the
+// R x R normal equations (Hadamard product of Grams, Cholesky factor,
+// inverse), the row solves, column norms, Grams and the fit are FP64.
+// Factor storage is FP32 or BF16 (double -> binary32 -> bfloat16, both
+// round-to-nearest-even).
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+
+namespace alto {
+namespace {
+
+constexpr int kT = 256;
+constexpr int kGramTile = 32;
+constexpr int kMaxParts = 1024;
+
+__device__ __forceinline__ double load_factor(const void *A, int prec, uint64_t q) {
+    if (prec == ALTO_PREC_BF16)
+        return (double)__uint_as_float((uint32_t)reinterpret_cast<const uint16_t *>(A)[q] << 16);
+    return (double)reinterpret_cast<const float *>(A)[q];
+}
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// Partial Grams: block (x, y) adds rows of chunk x into the 32x32 tile y of
+// A^T A.  partials[x][R][R].
+__global__ __launch_bounds__(kT) void gram_partial_k(const void *__restrict__ A, int prec, uint64_t I, int R,
+                                                     int nparts, double *__restrict__ partials) {
+    __shared__ double sa[32][kGramTile + 1];
+    __shared__ double sb[32][kGramTile + 1];
+    const int tiles = (R + kGramTile - 1) / kGramTile;
+    const int ta = blockIdx.y / tiles, tb = blockIdx.y % tiles;
+    const int a0 = ta * kGramTile, b0 = tb * kGramTile;
+    const uint64_t chunk = (I + nparts - 1) / nparts;
+    const uint64_t r0 = (uint64_t)blockIdx.x * chunk, r1 = min(I, r0 + chunk);
+    const int tx = threadIdx.x % kGramTile, ty = threadIdx.x / kGramTile;  // ty in 0..7
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (uint64_t i0 = r0; i0 < r1; i0 += 32) {
+        for (int q = threadIdx.x; q < 32 * kGramTile; q += kT) {
+            const int ri = q / kGramTile, cj = q % kGramTile;
+            const uint64_t i = i0 + ri;
+            const bool in = i < r1;
+            sa[ri][cj] = (in && a0 + cj < R) ? load_factor(A, prec, i * R + a0 + cj) : 0.0;
+            sb[ri][cj] = (in && b0 + cj < R) ? load_factor(A, prec, i * R + b0 + cj) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int ri = 0; ri < 32; ri++) {
+            const double bv = sb[ri][tx];
+#pragma unroll
+            for (int k = 0; k < 4; k++) acc[k] += sa[ri][ty + 8 * k] * bv;
+        }
+        __syncthreads();
+    }
+    double *P = partials + (uint64_t)blockIdx.x * R * R;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int a = a0 + ty + 8 * k, b = b0 + tx;
+        if (a < R && b < R) P[(uint64_t)a * R + b] = acc[k];
+    }
+}
+
+// Fixed-order sum of partials: out[e] = sum_p partials[p][e].
+__global__ __launch_bounds__(kT) void sum_parts_k(const double *__restrict__ partials, int nparts, int64_t n,
+                                                  double *__restrict__ out, const int *status) {
+    if (status && *status) return;
+    const int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (e >= n) return;
+    double s = 0.0;
+    for (int p = 0; p < nparts; p++) s += partials[(int64_t)p * n + e];
+    out[e] = s;
+}
+
+// V = Hadamard of the Grams of every mode except `skip`; Cholesky with one
+// ridge retry; Vinv = L^-T L^-1.  One block.  status <- 1 on failure.
+__global__ __launch_bounds__(kT) void normal_eq_k(const double *__restrict__ G, int N, int R, int skip,
+                                                  double *__restrict__ V, double *__restrict__ L,
+                                                  double *__restrict__ Vinv, int *status) {
+    __shared__ int bad;
+    __shared__ double ridge;
+    if (*status) return;
+    const int RR = R * R;
+    for (int e = threadIdx.x; e < RR; e += kT) {
+        double v = 1.0;
+        for (int m = 0; m < N; m++)
+            if (m != skip) v *= G[(int64_t)m * RR + e];
+        V[e] = v;
+    }
+    __syncthreads();
+    for (int attempt = 0; attempt < 2; attempt++) {
+        if (threadIdx.x == 0) {
+            bad = 0;
+            double tr = 0.0;
+            for (int r = 0; r < R; r++) tr += V[r * R + r];
+            ridge = attempt == 0 ? 0.0 : 1e-10 * tr / R;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < RR; e += kT) L[e] = 0.0;
+        __syncthreads();
+        for (int j = 0; j < R; j++) {
+            if (threadIdx.x == 0) {
+                double d = V[j * R + j] + ridge;
+                for (int k = 0; k < j; k++) d -= L[j * R + k] * L[j * R + k];
+                if (!(d > 0.0)) bad = 1;
+                L[j * R + j] = d > 0.0 ? sqrt(d) : 1.0;
+            }
+            __syncthreads();
+            const double djj = L[j * R + j];
+            for (int i = j + 1 + threadIdx.x; i < R; i += kT) {
+                double s = V[i * R + j];
+                for (int k = 0; k < j; k++) s -= L[i * R + k] * L[j * R + k];
+                L[i * R + j] = s / djj;
+            }
+            __syncthreads();
+        }
+        if (!bad) break;
+        __syncthreads();
+    }
+    if (bad) {
+        if (threadIdx.x == 0) *status = 1;
+        return;
+    }
+    // column c of Vinv: solve L y = e_c, then L^T x = y (x stored in Vinv[:, c])
+    for (int c = threadIdx.x; c < R; c += kT) {
+        for (int a = 0; a < R; a++) {
+            double s = a == c ? 1.0 : 0.0;
+            for (int k = 0; k < a; k++) s -= L[a * R + k] * Vinv[k * R + c];
+            Vinv[a * R + c] = s / L[a * R + a];
+        }
+        for (int a = R - 1; a >= 0; a--) {
+            double s = Vinv[a * R + c];
+            for (int k = a + 1; k < R; k++) s -= L[k * R + a] * Vinv[k * R + c];
+            Vinv[a * R + c] = s / L[a * R + a];
+        }
+    }
+}
+
+// Atmp(i, c) = sum_k Mn(i, k) Vinv(k, c) in FP64; per-block column sums of squares.
+__global__ __launch_bounds__(kT) void solve_rows_k(const float *__restrict__ Mn, const double *__restrict__ Vinv,
+                                                   uint64_t I, int R, double *__restrict__ Atmp,
+                                                   double *__restrict__ colsq_part, const int *status) {
+    extern __shared__ double sh[];
+    double *sv = sh;           // R*R when it fits, else unused
+    double *scol = sh + (R <= 64 ? R * R : 0);
+    if (*status) return;
+    const bool vin_lds = R <= 64;
+    if (vin_lds)
+        for (int e = threadIdx.x; e < R * R; e += kT) sv[e] = Vinv[e];
+    for (int e = threadIdx.x; e < R; e += kT) scol[e] = 0.0;
+    __syncthreads();
+    const double *vv = vin_lds ? sv : Vinv;
+    const uint64_t n = I * (uint64_t)R;
+    for (uint64_t e = (uint64_t)blockIdx.x * kT + threadIdx.x; e < n; e += (uint64_t)gridDim.x * kT) {
+        const uint64_t i = e / R;
+        const int c = (int)(e % R);
+        const float *m = Mn + i * R;
+        double s = 0.0;
+        for (int k = 0; k < R; k++) s += (double)m[k] * vv[k * R + c];
+        Atmp[e] = s;
+        atomicAdd(&scol[c], s * s);
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < R; c += kT) colsq_part[(uint64_t)blockIdx.x * R + c] = scol[c];
+}
+
+__global__ __launch_bounds__(kT) void lambda_k(const double *__restrict__ colsq_part, int nparts, int R,
+                                               double *__restrict__ lambda, const int *status) {
+    if (*status) return;
+    for (int c = threadIdx.x; c < R; c += kT) {
+        double s = 0.0;
+        for (int p = 0; p < nparts; p++) s += colsq_part[(uint64_t)p * R + c];
+        lambda[c] = sqrt(s);
+    }
+}
+
+// A(i, c) = store(Atmp(i, c) / lambda_c) in the storage precision; for the
+// last mode also the partial inner products sum_i lambda_c Mn(i,c) A(i,c).
+__global__ __launch_bounds__(kT) void normalize_k(const double *__restrict__ Atmp, const double *__restrict__ lambda,
+                                                  uint64_t I, int R, int prec, void *__restrict__ A,
+                                                  const float *__restrict__ Mn, double *__restrict__ inner_part,
+                                                  const int *status) {
+    __shared__ double red[kT / 64];
+    if (*status) return;
+    const uint64_t n = I * (uint64_t)R;
+    double inner = 0.0;
+    for (uint64_t e = (uint64_t)blockIdx.x * kT + threadIdx.x; e < n; e += (uint64_t)gridDim.x * kT) {
+        const int c = (int)(e % R);
+        const double lam = lambda[c];
+        const double a = lam > 0.0 ? Atmp[e] / lam : Atmp[e];
+        const float f = (float)a;
+        double stored;
+        if (prec == ALTO_PREC_BF16) {
+            const uint16_t b = f32_to_bf16_rne(f);
+            reinterpret_cast<uint16_t *>(A)[e] = b;
+            stored = (double)__uint_as_float((uint32_t)b << 16);
+        } else {
+            reinterpret_cast<float *>(A)[e] = f;
+            stored = (double)f;
+        }
+        if (inner_part) inner += lam * (double)Mn[e] * stored;
+    }
+    if (!inner_part) return;
+    for (int off = 32; off >= 1; off >>= 1) inner += __shfl_xor(inner, off);
+    if (__lane_id() == 0) red[threadIdx.x / 64] = inner;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < kT / 64; w++) s += red[w];
+        inner_part[blockIdx.x] = s;
+    }
+}
+
+// fit = 1 - sqrt(max(0, |X|^2 + |Xhat|^2 - 2 <X,Xhat>)) / |X|
+__global__ __launch_bounds__(kT) void fit_k(const double *__restrict__ G, int N, int R,
+                                            const double *__restrict__ lambda, const double *__restrict__ inner_part,
+                                            int nparts, double norm2, double *__restrict__ fit_out,
+                                            const int *status) {
+    __shared__ double red[kT / 64];
+    __shared__ double red2[kT / 64];
+    if (*status) return;
+    const int RR = R * R;
+    double xh = 0.0, in = 0.0;
+    for (int e = threadIdx.x; e < RR; e += kT) {
+        double h = lambda[e / R] * lambda[e % R];
+        for (int m = 0; m < N; m++) h *= G[(int64_t)m * RR + e];
+        xh += h;
+    }
+    for (int p = threadIdx.x; p < nparts; p += kT) in += inner_part[p];
+    for (int off = 32; off >= 1; off >>= 1) {
+        xh += __shfl_xor(xh, off);
+        in += __shfl_xor(in, off);
+    }
+    if (__lane_id() == 0) {
+        red[threadIdx.x / 64] = xh;
+        red2[threadIdx.x / 64] = in;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int w = 0; w < kT / 64; w++) {
+            a += red[w];
+            b += red2[w];
+        }
+        double r2 = norm2 + a - 2.0 * b;
+        if (r2 < 0.0) r2 = 0.0;
+        *fit_out = norm2 > 0.0 ? 1.0 - sqrt(r2) / sqrt(norm2) : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(kT) void round_bf16_k(const double *__restrict__ in, uint16_t *__restrict__ out,
+                                                   int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x; e < n; e += (int64_t)gridDim.x * kT)
+        out[e] = f32_to_bf16_rne((float)in[e]);
+}
+
+int parts_for(uint64_t I) {
+    const uint64_t p = (I + 63) / 64;
+    return (int)std::max<uint64_t>(1, std::min<uint64_t>(kMaxParts, p));
+}
+
+struct AlsWs {
+    float *Mn;
+    double *Atmp, *G, *V, *L, *Vinv, *parts, *colsq, *inner, *fit;
+    int *status;
+};
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+
+int launch_gram(const void *A, int prec, uint64_t I, int R, double *G, double *partials, int nparts,
+                hipStream_t s) {
+    const int tiles = (R + kGramTile - 1) / kGramTile;
+    gram_partial_k<<<dim3(nparts, tiles * tiles), kT, 0, s>>>(A, prec, I, R, nparts, partials);
+    const int64_t n = (int64_t)R * R;
+    sum_parts_k<<<(unsigned)((n + kT - 1) / kT), kT, 0, s>>>(partials, nparts, n, G, nullptr);
+    ALTO_HIP(hipGetLastError());
+    return ALTO_OK;
+}
+
+int launch_round_bf16(const double *in, uint16_t *out, int64_t n, hipStream_t s) {
+    if (n == 0) return ALTO_OK;
+    const int64_t g = std::min<int64_t>(65536, (n + kT - 1) / kT);
+    round_bf16_k<<<(unsigned)g, kT, 0, s>>>(in, out, n);
+    ALTO_HIP(hipGetLastError());
+    return ALTO_OK;
+}
+
+int cp_als_impl(alto_tensor *t, int R, int iters, int prec, void *const *factors, double *lambda, double *fit,
+                const alto_exec *ex, hipStream_t s) {
+    if (!t) return set_error(ALTO_E_INVAL, "null tensor handle");
+    if (R < 1 || R > ALTO_MAX_RANK) return set_error(ALTO_E_INVAL, "R must be in 1..256");
+    if (iters < 0) return set_error(ALTO_E_INVAL, "iters must be >= 0");
+    if (prec != ALTO_PREC_F32 && prec != ALTO_PREC_BF16) return set_error(ALTO_E_INVAL, "unknown precision");
+    if (!factors || !lambda || (iters > 0 && !fit)) return set_error(ALTO_E_INVAL, "null argument");
+    for (int n = 0; n < t->N; n++)
+        if (!factors[n]) return set_error(ALTO_E_INVAL, "null factor pointer");
+    if (t->nnz == 0) return set_error(ALTO_E_INVAL, "CP-ALS of an empty tensor");
+    const int N = t->N;
+    uint64_t maxI = 0;
+    for (int n = 0; n < N; n++) maxI = std::max(maxI, t->dims[n]);
+    const int RR = R * R;
+    const int P = parts_for(maxI);
+    // the MTTKRP output and the FP64 solve buffer live in their own allocation
+    // (the tensor workspace may be regrown by a re-partition)
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t o = off;
+        off += align256(b);
+        return o;
+    };
+    const size_t oMn = take(sizeof(float) * maxI * R), oAt = take(sizeof(double) * maxI * R),
+                 oG = take(sizeof(double) * N * RR), oV = take(sizeof(double) * RR), oL = take(sizeof(double) * RR),
+                 oVi = take(sizeof(double) * RR), oP = take(sizeof(double) * (size_t)P * RR),
+                 oC = take(sizeof(double) * (size_t)kMaxParts * R), oI = take(sizeof(double) * kMaxParts),
+                 oF = take(sizeof(double) * std::max(1, iters)), oS = take(sizeof(int));
+    char *base = nullptr;
+    ALTO_HIP(hipMalloc(&base, off));
+    AlsWs w;
+    w.Mn = (float *)(base + oMn);
+    w.Atmp = (double *)(base + oAt);
+    w.G = (double *)(base + oG);
+    w.V = (double *)(base + oV);
+    w.L = (double *)(base + oL);
+    w.Vinv = (double *)(base + oVi);
+    w.parts = (double *)(base + oP);
+    w.colsq = (double *)(base + oC);
+    w.inner = (double *)(base + oI);
+    w.fit = (double *)(base + oF);
+    w.status = (int *)(base + oS);
+    int rc = ALTO_OK;
+    auto done = [&](int code) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(base);
+        return code;
+    };
+#define ALS_HIP(call)                                            \
+    do {                                                         \
+        hipError_t e_ = (call);                                  \
+        if (e_ != hipSuccess) return done(hip_error(e_, #call)); \
+    } while (0)
+    ALS_HIP(hipMemsetAsync(w.status, 0, sizeof(int), s));
+    for (int n = 0; n < N; n++) {
+        rc = launch_gram(factors[n], prec, t->dims[n], R, w.G + (size_t)n * RR, w.parts, parts_for(t->dims[n]), s);
+        if (rc) return done(rc);
+    }
+    const size_t solve_lds = sizeof(double) * ((R <= 64 ? RR : 0) + R);
+    for (int it = 0; it < iters; it++) {
+        for (int n = 0; n < N; n++) {
+            const uint64_t I = t->dims[n];
+            rc = plan_and_run_mttkrp(t, (const void *const *)factors, R, prec, n, w.Mn, ex, s);
+            if (rc) return done(rc);
+            normal_eq_k<<<1, kT, 0, s>>>(w.G, N, R, n, w.V, w.L, w.Vinv, w.status);
+            const uint64_t elems = I * (uint64_t)R;
+            const int gsolve = (int)std::min<uint64_t>(kMaxParts, (elems + kT - 1) / kT);
+            solve_rows_k<<<gsolve, kT, solve_lds, s>>>(w.Mn, w.Vinv, I, R, w.Atmp, w.colsq, w.status);
+            lambda_k<<<1, kT, 0, s>>>(w.colsq, gsolve, R, lambda, w.status);
+            const bool last = n == N - 1;
+            normalize_k<<<gsolve, kT, 0, s>>>(w.Atmp, lambda, I, R, prec, factors[n], w.Mn,
+                                               last ? w.inner : nullptr, w.status);
+            const int Pn = parts_for(I);
+            const int tiles = (R + kGramTile - 1) / kGramTile;
+            gram_partial_k<<<dim3(Pn, tiles * tiles), kT, 0, s>>>(factors[n], prec, I, R, Pn, w.parts);
+            sum_parts_k<<<(unsigned)((RR + kT - 1) / kT), kT, 0, s>>>(w.parts, Pn, RR, w.G + (size_t)n * RR,
+                                                                     w.status);
+            if (last) fit_k<<<1, kT, 0, s>>>(w.G, N, R, lambda, w.inner, gsolve, t->norm2, w.fit + it, w.status);
+            ALS_HIP(hipGetLastError());
+        }
+    }
+    int st = 0;
+    ALS_HIP(hipMemcpyAsync(&st, w.status, sizeof(int), hipMemcpyDeviceToHost, s));
+    if (iters > 0) ALS_HIP(hipMemcpyAsync(fit, w.fit, sizeof(double) * iters, hipMemcpyDeviceToHost, s));
+    ALS_HIP(hipStreamSynchronize(s));
+#undef ALS_HIP
+    if (st) return done(set_error(ALTO_E_NOTSPD, "normal-equation matrix is not positive definite"));
+    return done(ALTO_OK);
+}
+
+}  // namespace alto

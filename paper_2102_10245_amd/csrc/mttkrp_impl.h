@@ -1,0 +1,366 @@
+// Mode-n MTTKRP on an ALTO tensor (Algorithms 1 and 2 of the ALTO paper),
+// written for CDNA4 (64-lane waves, 160 KiB LDS per compute unit, one L2 per
+// XCD).
+//
+// One workgroup processes one line segment.  The segment is cut into NG
+// contiguous sub-ranges, one per lane group of G = R/VEC lanes; each lane
+// owns VEC consecutive rank columns, so a factor row is gathered with one
+// 16-byte load per lane.  Waves run independently (no workgroup barrier in
+// the main loop).  Per tile of G nonzeros per group:
+//   - every lane loads one nonzero of its own group (coalesced, prefetched one
+//     tile ahead) and de-linearizes it (bit-level scatter of the index);
+//   - the group then walks its G nonzeros in order: coordinates and value come
+//     from the owning lane by cross-lane shuffle, the N-1 factor rows are
+//     gathered and multiplied, and the product is added to a register
+//     accumulator while the output row repeats; when the row changes the
+//     accumulator is flushed.
+// A flush goes either to Temp (Algorithm 2, local staging: LDS rows
+// [T^s, T^e] of the segment's mode interval, merged into the output when the
+// segment is done: plain stores for rows no other segment covers, FP32 atomics
+// otherwise) or straight out with FP32 atomics (Algorithm 2, atomic update).
+// Atomic updates can target a per-XCD replica of the output (chosen by the
+// XCC id register) so that the lines a replica owns are only ever touched by
+// one L2; a reduction adds the replicas into the output afterwards.  The
+// atomics are device-scope either way, so the result does not depend on which
+// XCD a workgroup runs on.
+#pragma once
+
+#include "common.h"
+
+namespace alto {
+
+struct FactorPtrs {
+    const void *p[kMaxModes];
+};
+
+constexpr uint32_t kNoRow = 0xffffffffu;
+constexpr int kMaxReplicas = 16;
+
+template <typename FT>
+struct FactorLoad;
+
+template <>
+struct FactorLoad<float> {
+    static constexpr int kVec = 4;
+    __device__ __forceinline__ static void load(const void *base, uint64_t off, float (&x)[4]) {
+        const float4 q = *reinterpret_cast<const float4 *>(reinterpret_cast<const float *>(base) + off);
+        x[0] = q.x;
+        x[1] = q.y;
+        x[2] = q.z;
+        x[3] = q.w;
+    }
+    __device__ __forceinline__ static float load1(const void *base, uint64_t off) {
+        return reinterpret_cast<const float *>(base)[off];
+    }
+};
+
+__device__ __forceinline__ float bf16_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
+
+template <>
+struct FactorLoad<uint16_t> {
+    static constexpr int kVec = 8;
+    __device__ __forceinline__ static void load(const void *base, uint64_t off, float (&x)[8]) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(reinterpret_cast<const uint16_t *>(base) + off);
+        x[0] = bf16_to_f32(q.x & 0xffffu);
+        x[1] = bf16_to_f32(q.x >> 16);
+        x[2] = bf16_to_f32(q.y & 0xffffu);
+        x[3] = bf16_to_f32(q.y >> 16);
+        x[4] = bf16_to_f32(q.z & 0xffffu);
+        x[5] = bf16_to_f32(q.z >> 16);
+        x[6] = bf16_to_f32(q.w & 0xffffu);
+        x[7] = bf16_to_f32(q.w >> 16);
+    }
+    __device__ __forceinline__ static float load1(const void *base, uint64_t off) {
+        return bf16_to_f32(reinterpret_cast<const uint16_t *>(base)[off]);
+    }
+};
+
+// Compile-time shape of one instantiation.  RT = 0: any rank (one 64-lane
+// wave per nonzero, up to four columns per lane).  NT = 0: any order <= 8.
+template <int NT, int RT, typename FT>
+struct MtCfg {
+    static constexpr int kVec = RT ? FactorLoad<FT>::kVec : 1;
+    static constexpr int kG = RT ? RT / kVec : 64;            // lanes per nonzero
+    static constexpr int kGPW = 64 / kG;                      // lane groups per wave
+    static constexpr int kCols = RT ? 1 : 4;                  // column chunks per lane (generic rank)
+    static constexpr int kNMax = NT ? NT : kMaxModes;
+    static constexpr int kU = (NT == 0 || RT == 0) ? 1 : (kG >= 2 ? 2 : 1);  // nonzeros in flight per group
+};
+
+// LDS row stride of Temp: one float of padding spreads rows over the banks.
+__host__ __device__ inline int temp_stride(int R) { return R + 1; }
+
+__device__ __forceinline__ uint32_t xcc_id() {
+    // hwreg(HW_REG_XCC_ID, 0, 4): id 20, offset 0, 4 bits
+    return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 0xfu;
+}
+
+template <typename K, int NT, int RT, typename FT, bool kStaged>
+__global__ __launch_bounds__(1024) void mttkrp_k(
+    const K *__restrict__ keys, const float *__restrict__ vals, const int64_t *__restrict__ seg,
+    const uint32_t *__restrict__ ivl, const uint32_t *__restrict__ cov, FactorPtrs fac, int R_rt, int N_rt, int mode,
+    RunTable tab, float *__restrict__ out, float *__restrict__ rep, uint64_t rep_stride, int nrep,
+    const int32_t *__restrict__ seg_list, int n_list) {
+    using C = MtCfg<NT, RT, FT>;
+    constexpr int VEC = C::kVec, G = C::kG, GPW = C::kGPW, NM = C::kNMax, NCOL = C::kCols, U = C::kU;
+    const int N = NT ? NT : N_rt;
+    const int R = RT ? RT : R_rt;
+    extern __shared__ float temp[];
+
+    // XCD-aware order: consecutive list entries (neighbouring segments, which
+    // touch neighbouring factor rows) go to the same L2.
+    const int per = (n_list + 7) / 8;
+    const int li = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (li >= n_list) return;
+    const int l = seg_list[li];
+
+    const int64_t sb = seg[l], S = seg[l + 1] - sb;
+    const int lane = __lane_id(), wave = threadIdx.x / 64;
+    const int NG = blockDim.x / G;
+    const int gw = lane / G, c = lane % G;
+    const int g = wave * GPW + gw;
+    const int64_t gb = sb + (S * g) / NG;
+    const int64_t ge = sb + (S * (g + 1)) / NG;
+    const int64_t maxlen = (S + NG - 1) / NG;
+    const int ntiles = (int)((maxlen + G - 1) / G);
+
+    float *const atom = rep ? rep + (uint64_t)(xcc_id() % (uint32_t)nrep) * rep_stride : out;
+    const int RP = temp_stride(R);
+
+    uint32_t lo = 0, width = 0;
+    if constexpr (kStaged) {
+        lo = ivl[((int64_t)l * N + mode) * 2 + 0];
+        width = ivl[((int64_t)l * N + mode) * 2 + 1] - lo + 1;
+        for (int q = threadIdx.x; q < (int)width * RP; q += blockDim.x) temp[q] = 0.f;
+        __syncthreads();
+    }
+
+    uint32_t cur = kNoRow;
+    float acc[NCOL][VEC];
+#pragma unroll
+    for (int a = 0; a < NCOL; a++)
+#pragma unroll
+        for (int e = 0; e < VEC; e++) acc[a][e] = 0.f;
+
+    auto flush = [&](uint32_t row, const float (&v)[NCOL][VEC]) {
+#pragma unroll
+        for (int a = 0; a < NCOL; a++) {
+            const int col0 = RT ? c * VEC : c + 64 * a;
+            if (!RT && col0 >= R) continue;
+            if constexpr (kStaged) {
+                float *dst = temp + (uint64_t)(row - lo) * RP + col0;
+#pragma unroll
+                for (int e = 0; e < VEC; e++) atomicAdd(dst + e, v[a][e]);
+            } else {
+                float *dst = atom + (uint64_t)row * R + col0;
+#pragma unroll
+                for (int e = 0; e < VEC; e++) unsafeAtomicAdd(dst + e, v[a][e]);
+            }
+        }
+    };
+
+    // Flushes found while combining a batch are issued only after the next
+    // batch's gathers, so that waiting for those loads does not also wait for
+    // the atomics (loads and atomics share one in-order memory counter).
+    bool pend[U];
+    uint32_t prow[U];
+    float pacc[U][NCOL][VEC];
+#pragma unroll
+    for (int u = 0; u < U; u++) pend[u] = false;
+
+    // prefetch the first tile: lane c of group g owns items gb + t*G + c
+    int64_t pos = gb + c;
+    bool ok_n = pos < ge;
+    K key_n = ok_n ? keys[pos] : KeyOps<K>::zero();
+    float val_n = ok_n ? vals[pos] : 0.f;
+
+    for (int t = 0; t < ntiles; t++) {
+        const K key = key_n;
+        const float v = val_n;
+        const bool ok = ok_n;
+        pos += G;
+        ok_n = pos < ge;
+        if (ok_n) {
+            key_n = keys[pos];
+            val_n = vals[pos];
+        }
+        // de-linearize this lane's nonzero
+        uint32_t idx[NM];
+#pragma unroll
+        for (int m = 0; m < NM; m++) idx[m] = (m < N && ok) ? extract_mode(key, tab, m) : 0u;
+        uint32_t myrow = kNoRow;
+#pragma unroll
+        for (int m = 0; m < NM; m++)
+            if (m == mode && ok) myrow = idx[m];
+
+        for (int k0 = 0; k0 < G; k0 += U) {
+            uint32_t rows[U];
+            float vv[U];
+            float f[U][NM][NCOL][VEC];
+            // (1) gathers of this batch
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int src = gw * G + k0 + u;
+                rows[u] = G == 1 ? myrow : (uint32_t)__shfl((int)myrow, src);
+                vv[u] = G == 1 ? v : __shfl(v, src);
+#pragma unroll
+                for (int m = 0; m < NM; m++) {
+                    if (m >= N || m == mode) continue;
+                    const uint32_t im = G == 1 ? idx[m] : (uint32_t)__shfl((int)idx[m], src);
+                    const uint64_t rowoff = (uint64_t)im * (uint64_t)R;
+                    if constexpr (RT != 0) {
+                        FactorLoad<FT>::load(fac.p[m], rowoff + (uint64_t)c * VEC, f[u][m][0]);
+                    } else {
+#pragma unroll
+                        for (int a = 0; a < NCOL; a++) {
+                            const int col = c + 64 * a;
+                            f[u][m][a][0] = col < R ? FactorLoad<FT>::load1(fac.p[m], rowoff + col) : 0.f;
+                        }
+                    }
+                }
+            }
+            // (2) the previous batch's flushes
+#pragma unroll
+            for (int u = 0; u < U; u++)
+                if (pend[u]) {
+                    flush(prow[u], pacc[u]);
+                    pend[u] = false;
+                }
+            // (3) products and run combining
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                if (rows[u] == kNoRow) continue;
+                float p[NCOL][VEC];
+#pragma unroll
+                for (int a = 0; a < NCOL; a++)
+#pragma unroll
+                    for (int e = 0; e < VEC; e++) p[a][e] = vv[u];
+#pragma unroll
+                for (int m = 0; m < NM; m++) {
+                    if (m >= N || m == mode) continue;
+#pragma unroll
+                    for (int a = 0; a < NCOL; a++)
+#pragma unroll
+                        for (int e = 0; e < VEC; e++) p[a][e] *= f[u][m][a][e];
+                }
+                if (rows[u] != cur) {
+                    if (cur != kNoRow) {
+                        pend[u] = true;
+                        prow[u] = cur;
+#pragma unroll
+                        for (int a = 0; a < NCOL; a++)
+#pragma unroll
+                            for (int e = 0; e < VEC; e++) pacc[u][a][e] = acc[a][e];
+                    }
+                    cur = rows[u];
+#pragma unroll
+                    for (int a = 0; a < NCOL; a++)
+#pragma unroll
+                        for (int e = 0; e < VEC; e++) acc[a][e] = p[a][e];
+                } else {
+#pragma unroll
+                    for (int a = 0; a < NCOL; a++)
+#pragma unroll
+                        for (int e = 0; e < VEC; e++) acc[a][e] += p[a][e];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++)
+        if (pend[u]) flush(prow[u], pacc[u]);
+    if (cur != kNoRow) flush(cur, acc);
+    if constexpr (kStaged) {
+        // merge Temp into the output (the pull of Algorithm 2 for this segment)
+        __syncthreads();
+        const int total = (int)width * R;
+        for (int q = threadIdx.x; q < total; q += blockDim.x) {
+            const int r = q / R, col = q - r * R;
+            const float v = temp[r * RP + col];
+            if (v == 0.f) continue;
+            const uint32_t row = lo + (uint32_t)r;
+            if (cov[row] == 1u) out[(uint64_t)row * R + col] = v;
+            else unsafeAtomicAdd(atom + (uint64_t)row * R + col, v);
+        }
+    }
+}
+
+struct MtLaunch {
+    const void *keys;
+    const float *vals;
+    const int64_t *seg;
+    const uint32_t *ivl;
+    const uint32_t *cov;
+    FactorPtrs fac;
+    int R, N, mode;
+    RunTable tab;
+    float *out;
+    float *rep;        // replicas (nullptr: atomics straight to out)
+    uint64_t rep_stride;
+    int nrep;
+    const int32_t *list;
+    int n_list;
+    int staged;
+    int temp_rows;     // LDS Temp rows to reserve (staged launches)
+    int threads;       // workgroup size (multiple of 64, <= 1024)
+};
+
+template <typename K, int NT, int RT, typename FT>
+int launch_mt_cfg(const MtLaunch &a, hipStream_t s) {
+    if (a.n_list <= 0) return ALTO_OK;
+    const size_t lds = a.staged ? (size_t)a.temp_rows * temp_stride(a.R) * 4 : 0;
+    const int per = (a.n_list + 7) / 8;
+    const unsigned grid = (unsigned)per * 8;
+    auto kern = a.staged ? mttkrp_k<K, NT, RT, FT, true> : mttkrp_k<K, NT, RT, FT, false>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute(MaxDynamicSharedMemorySize)");
+    }
+    kern<<<grid, a.threads, lds, s>>>((const K *)a.keys, a.vals, a.seg, a.ivl, a.cov, a.fac, a.R, a.N, a.mode, a.tab,
+                                      a.out, a.rep, a.rep_stride, a.nrep, a.list, a.n_list);
+    ALTO_HIP(hipGetLastError());
+    return ALTO_OK;
+}
+
+template <typename K, int NT, typename FT>
+int launch_mt_r(const MtLaunch &a, hipStream_t s) {
+    switch (a.R) {
+        case 8: return launch_mt_cfg<K, NT, 8, FT>(a, s);
+        case 16: return launch_mt_cfg<K, NT, 16, FT>(a, s);
+        case 32: return launch_mt_cfg<K, NT, 32, FT>(a, s);
+        case 64: return launch_mt_cfg<K, NT, 64, FT>(a, s);
+        default: return launch_mt_cfg<K, NT, 0, FT>(a, s);
+    }
+}
+
+template <typename K, typename FT>
+int launch_mt_n(const MtLaunch &a, hipStream_t s) {
+    switch (a.N) {
+        case 3: return launch_mt_r<K, 3, FT>(a, s);
+        case 4: return launch_mt_r<K, 4, FT>(a, s);
+        case 5: return launch_mt_r<K, 5, FT>(a, s);
+        default: return launch_mt_r<K, 0, FT>(a, s);
+    }
+}
+
+// One translation unit per (key width, precision) keeps compile times parallel.
+int launch_mt_k32_f32(const MtLaunch &a, hipStream_t s);
+int launch_mt_k64_f32(const MtLaunch &a, hipStream_t s);
+int launch_mt_k128_f32(const MtLaunch &a, hipStream_t s);
+int launch_mt_k32_bf16(const MtLaunch &a, hipStream_t s);
+int launch_mt_k64_bf16(const MtLaunch &a, hipStream_t s);
+int launch_mt_k128_bf16(const MtLaunch &a, hipStream_t s);
+
+inline int launch_mt(const MtLaunch &a, int key_bits, int prec, hipStream_t s) {
+    const bool bf = prec == ALTO_PREC_BF16;
+    if (key_bits == 32) return bf ? launch_mt_k32_bf16(a, s) : launch_mt_k32_f32(a, s);
+    if (key_bits == 64) return bf ? launch_mt_k64_bf16(a, s) : launch_mt_k64_f32(a, s);
+    return bf ? launch_mt_k128_bf16(a, s) : launch_mt_k128_f32(a, s);
+}
+
+// out[e] += sum of the nrep replicas at e, for e < n
+int launch_replica_reduce(float *out, const float *rep, uint64_t stride, int nrep, uint64_t n, hipStream_t s);
+// number of distinct XCC ids the device reports (0 if it cannot tell)
+int device_xcc_count();
+
+}  // namespace alto

@@ -1,0 +1,66 @@
+"""The C-ABI library loads and exports every entry point include/alto.h
+declares; argument errors come back as exact codes without touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2102_10245_amd as alto
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "alto.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*\**\s*(\w+)\s*\(", src, flags=re.M)))
+
+
+def test_header_declares_expected_calls():
+    names = _declared()
+    for n in ("alto_build", "alto_mttkrp", "cp_als", "alto_select", "alto_free", "alto_last_error"):
+        assert n in names
+    assert set(names) == set(alto.EXPORTS)
+
+
+@pytest.mark.skipif(not alto.lib_available(), reason="libalto.so not built")
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(alto.LIB_PATH)
+    for n in _declared():
+        assert hasattr(L, n), n
+
+
+@pytest.mark.skipif(not alto.lib_available(), reason="libalto.so not built")
+def test_argument_errors_without_device_work():
+    L = alto.lib()
+    h = ctypes.c_void_p()
+    dims = (ctypes.c_uint64 * 3)(4, 8, 2)
+    # N outside 2..8
+    assert L.alto_build(None, None, 0, dims, 1, None, ctypes.byref(h), None) == alto.E_INVAL
+    assert L.alto_build(None, None, 0, dims, 9, None, ctypes.byref(h), None) == alto.E_INVAL
+    # a zero dimension and one above 2^32
+    bad = (ctypes.c_uint64 * 3)(4, 0, 2)
+    assert L.alto_build(None, None, 0, bad, 3, None, ctypes.byref(h), None) == alto.E_INVAL
+    big = (ctypes.c_uint64 * 3)(4, 2 ** 32 + 1, 2)
+    assert L.alto_build(None, None, 0, big, 3, None, ctypes.byref(h), None) == alto.E_INVAL
+    assert b"dims" in L.alto_last_error()
+    # null coordinates with nnz > 0
+    assert L.alto_build(None, None, 5, dims, 3, None, ctypes.byref(h), None) == alto.E_INVAL
+    # null handles
+    assert L.alto_mttkrp(None, None, 16, 0, 0, None, None, None) == alto.E_INVAL
+    assert L.cp_als(None, 16, 1, 0, None, None, None, None, None) == alto.E_INVAL
+    assert L.alto_partition(None, 4, None) == alto.E_INVAL
+    assert L.alto_info(None, None) == alto.E_INVAL
+    ex = alto._Exec()
+    assert L.alto_select(None, 0, 16, 0, ctypes.byref(ex)) == alto.E_INVAL
+    # selector weights with a bad header
+    import numpy as np
+    w = np.zeros(10, np.float32)
+    assert L.alto_selector_load(w.ctypes.data, w.size) == alto.E_INVAL
+    assert L.alto_selector_load(None, 0) == alto.OK
+    # MLP size checks
+    assert L.alto_mlp_forward(0, 1, 1, 1, None, None, None, None, None, None, None) == alto.E_INVAL
+    assert L.alto_mlp_adam(0, None, None, None, None, 0.1, 0.9, 0.99, 1e-8, 1, None) == alto.E_INVAL
+    assert L.alto_round_bf16(None, None, -1, None) == alto.E_INVAL
+    L.alto_free(None)

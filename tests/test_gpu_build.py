@@ -1,0 +1,130 @@
+"""GPU format generation vs the oracle, bit for bit: linearized indices,
+their order, coalescing, segment bounds, mode intervals and coverage."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2102_10245_amd as alto
+import synth
+from gpu_common import gpu_ok, keys_numpy, oracle_alto, small, to_dev
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_ok(), reason="needs a GPU")]
+
+CASES = [
+    # (recipe, key_bits override, L)
+    (synth.WORKLOADS["uniform3_1000x800x600_100k"], 0, 2048),
+    (small("zipf3_2Mx2Mx20k_50M", 200_000), 0, 1024),
+    (small("zipf4_1Mx100kx10kx500_150M", 300_000), 0, 2048),
+    (small("zipf5_10Mx5Mx2Mx100kx1k_200M", 150_000), 0, 512),
+    (synth.Recipe("wide_key_short_index", (1000, 800, 600), 50_001, (0.8, 0, 1.3), seed=3), 128, 97),
+    (synth.Recipe("pow2_dims", (1024, 2, 4096, 1, 64), 70_000, (0, 0, 1.1, 0, 0), seed=4), 64, 300),
+    (synth.Recipe("order2", (5000, 3000), 40_000, (1.0, 0), seed=5), 0, 64),
+    (synth.Recipe("order6", (40, 30, 20, 10, 7, 3), 60_000, (0.5,) * 6, seed=6), 0, 333),
+    (synth.Recipe("order8", (9, 8, 7, 6, 5, 4, 3, 2), 30_000, (), seed=7), 0, 40),
+]
+
+
+@pytest.mark.parametrize("rec,kb,L", CASES, ids=[c[0].name for c in CASES])
+def test_build_bit_exact(rec, kb, L):
+    print("case", rec.name, rec.dims, rec.nnz, kb, L, flush=True)
+    coords, vals = synth.coo(rec)
+    c, v = to_dev(coords, vals)
+    t = alto.AltoTensor.build(c, v, rec.dims, key_bits=kb, num_segments=L)
+    info = t.info()
+    (olo, ohi), ov, lay, _ = oracle_alto(rec.dims, coords, vals)
+    assert info["index_bits"] == lay.B
+    assert info["masks"] == lay.masks
+    assert info["key_bits"] == (kb or lay.W)
+    assert info["nnz_in"] == rec.nnz and info["nnz"] == len(olo)
+    keys, gv = t.export_keys()
+    glo, ghi = keys_numpy(keys, info["key_bits"])
+    assert np.array_equal(glo, olo) and np.array_equal(ghi, ohi)
+    gv = gv.cpu().numpy().astype(np.float64)
+    if info["nnz"] == rec.nnz:
+        assert np.array_equal(gv, ov)  # a permutation of the inputs, bit for bit
+    else:
+        assert np.allclose(gv, ov, rtol=2e-6, atol=0)  # FP32 sums of repeated coordinates
+    assert info["norm2"] == pytest.approx(float(np.sum(ov * ov)), rel=1e-6)
+    seg, ivl = t.export_partition()
+    oseg = oracle.partition(len(olo), L)
+    assert np.array_equal(seg.cpu().numpy(), oseg)
+    oivl = oracle.intervals(lay, oseg, (olo, ohi))
+    assert np.array_equal(ivl.cpu().numpy().view(np.uint32), oivl)
+    for n in range(len(rec.dims)):
+        if rec.dims[n] * len(oseg) > 2e8:
+            continue  # the brute-force coverage would take too long
+        cov = t.export_coverage(n).cpu().numpy().view(np.uint32)
+        assert np.array_equal(cov, oracle.coverage(oivl, n, rec.dims[n])), n
+    t.close()
+
+
+def test_duplicates_coalesced_in_input_order():
+    torch = pytest.importorskip("torch")
+    dims = (7, 5, 3)
+    coords = np.array([[1, 1, 6, 1, 0, 1], [2, 2, 4, 2, 0, 2], [0, 0, 2, 0, 0, 0]], np.uint32)
+    vals = np.array([1.0, 2.0, 3.0, 1e-8, 5.0, 4.0], np.float32)
+    c, v = to_dev(coords, vals)
+    t = alto.AltoTensor.build(c, v, dims, num_segments=2)
+    assert t.info()["nnz"] == 3
+    _, gv = t.export_keys()
+    (olo, _), ov, _, _ = oracle_alto(dims, coords, vals)
+    # the repeated coordinate (1,2,0) is summed in FP32 in input order: ((1+2)+1e-8)+4
+    expect = np.float32(np.float32(np.float32(1.0) + np.float32(2.0)) + np.float32(1e-8)) + np.float32(4.0)
+    got = dict(zip(olo.tolist(), gv.cpu().numpy().tolist()))
+    lay = oracle.layout(dims)
+    k = int(oracle.encode(lay, np.array([[1], [2], [0]], np.uint32))[0][0])
+    assert got[k] == expect
+    t.close()
+
+
+@pytest.mark.parametrize("M,L", [(0, 16), (1, 16), (5, 16), (4097, 4096)])
+def test_tiny_and_empty(M, L):
+    rec = synth.Recipe("tiny", (30, 20, 10), M, (), seed=11)
+    coords, vals = synth.coo(rec)
+    torch = pytest.importorskip("torch")
+    if M == 0:
+        c = torch.zeros((3, 0), dtype=torch.int32, device="cuda")
+        v = torch.zeros(0, dtype=torch.float32, device="cuda")
+    else:
+        c, v = to_dev(coords, vals)
+    t = alto.AltoTensor.build(c, v, rec.dims, num_segments=L)
+    info = t.info()
+    (olo, ohi), ov, lay, _ = oracle_alto(rec.dims, coords, vals)
+    assert info["nnz"] == len(olo) and info["num_segments"] == min(L, len(olo))
+    if M:
+        keys, _ = t.export_keys()
+        glo, _ = keys_numpy(keys, info["key_bits"])
+        assert np.array_equal(glo, olo)
+        seg, ivl = t.export_partition()
+        oseg = oracle.partition(len(olo), L)
+        assert np.array_equal(seg.cpu().numpy(), oseg)
+        assert np.array_equal(ivl.cpu().numpy().view(np.uint32), oracle.intervals(lay, oseg, (olo, ohi)))
+    t.close()
+
+
+def test_out_of_range_coordinate_is_reported():
+    coords = np.array([[0, 3], [0, 1], [0, 1]], np.uint32)  # 3 is not below dim 3
+    c, v = to_dev(coords, np.ones(2, np.float32))
+    with pytest.raises(alto.AltoError) as e:
+        alto.AltoTensor.build(c, v, (3, 2, 2))
+    assert e.value.code == alto.E_RANGE
+
+
+def test_too_wide_index_rejected():
+    c, v = to_dev(np.zeros((5, 1), np.uint32), np.ones(1, np.float32))
+    with pytest.raises(alto.AltoError) as e:
+        alto.AltoTensor.build(c, v, (2 ** 32,) * 5)
+    assert e.value.code == alto.E_TOO_WIDE
+    with pytest.raises(alto.AltoError) as e:
+        alto.AltoTensor.build(c[:3], v, (2 ** 20,) * 3, key_bits=32)
+    assert e.value.code == alto.E_TOO_WIDE
+
+
+def test_bf16_rounding_bits_match_oracle():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(8)
+    x = np.concatenate([rng.standard_normal(100000) * 10.0 ** rng.integers(-20, 20, 100000),
+                        [0.0, -0.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -9, np.inf, -np.inf, np.nan, 3.4e38, 1e-45]])
+    got = alto.round_bf16(torch.from_numpy(x).cuda()).cpu().numpy().view(np.uint16)
+    ref, _ = oracle.bf16_round(x)
+    assert np.array_equal(got, ref)

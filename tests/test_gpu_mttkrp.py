@@ -1,0 +1,139 @@
+"""GPU MTTKRP vs the FP64 oracle (relative Frobenius error <= 1e-5 for the
+FP32 path; the BF16 path reads factors that are exact in bfloat16, so the
+same bound applies to it against the oracle on those factors)."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2102_10245_amd as alto
+import synth
+from gpu_common import factors_dev, gpu_ok, rel_fro, small, to_dev
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_ok(), reason="needs a GPU")]
+
+TOL = 1e-5
+
+CASES = [
+    (synth.WORKLOADS["uniform3_1000x800x600_100k"], 16, 0),
+    (small("zipf3_2Mx2Mx20k_50M", 400_000), 16, 0),
+    (small("zipf3_2Mx2Mx20k_50M", 300_000), 64, 0),
+    (small("zipf4_1Mx100kx10kx500_150M", 600_000), 32, 0),
+    (small("zipf5_10Mx5Mx2Mx100kx1k_200M", 300_000), 32, 0),
+    (synth.Recipe("r8_order3", (300, 200, 100), 80_000, (1.0, 0, 0.5), seed=21), 8, 100),
+    (synth.Recipe("generic_r24", (500, 400, 30), 50_000, (0.9, 0.3, 0), seed=22), 24, 0),
+    (synth.Recipe("generic_r5_order2", (3000, 2000), 60_000, (1.2, 0), seed=23), 5, 64),
+    (synth.Recipe("generic_r100_order6", (20, 18, 16, 14, 12, 10), 40_000, (0.7,) * 6, seed=24), 100, 77),
+    (synth.Recipe("r256", (400, 300, 20), 20_000, (0, 0.8, 0), seed=25), 256, 0),
+    (synth.Recipe("unit_modes", (1, 700, 1, 90), 30_000, (0, 1.1, 0, 0), seed=26), 16, 0),
+]
+
+
+def _run_case(rec, R, L, strategies=("atomic", "staged", "auto"), precs=("f32", "bf16")):
+    coords, vals = synth.coo(rec)
+    c, v = to_dev(coords, vals)
+    t = alto.AltoTensor.build(c, v, rec.dims, num_segments=L)
+    fs = synth.factors(rec.seed + 1, rec.dims, R)
+    for mode in range(len(rec.dims)):
+        ref = oracle.mttkrp(rec.dims, coords, vals, fs, mode)
+        for prec in precs:
+            fd = factors_dev(fs, prec)
+            for st in strategies:
+                print("case", rec.name, "R", R, "mode", mode, prec, st, flush=True)
+                out = t.mttkrp(fd, mode, strategy=st).cpu().numpy()
+                err = rel_fro(out, ref)
+                assert err <= TOL, (rec.name, mode, prec, st, err)
+    t.close()
+
+
+@pytest.mark.parametrize("rec,R,L", CASES, ids=[c[0].name + "_R%d" % c[1] for c in CASES])
+def test_mttkrp_parity(rec, R, L):
+    _run_case(rec, R, L)
+
+
+@pytest.mark.parametrize("L", [1, 3, 1000, 100_000])
+def test_mttkrp_partition_extremes(L):
+    """One segment, a few, many, and more segments than nonzeros."""
+    rec = small("zipf4_1Mx100kx10kx500_150M", 20_000)
+    _run_case(rec, 16, L, precs=("f32",))
+
+
+def test_repartition_through_exec():
+    rec = small("zipf3_2Mx2Mx20k_50M", 100_000)
+    coords, vals = synth.coo(rec)
+    c, v = to_dev(coords, vals)
+    t = alto.AltoTensor.build(c, v, rec.dims)
+    fs = synth.factors(5, rec.dims, 16)
+    fd = factors_dev(fs)
+    ref = oracle.mttkrp(rec.dims, coords, vals, fs, 1)
+    for L in (128, 4096, 7):
+        out = t.mttkrp(fd, 1, strategy="staged", num_segments=L).cpu().numpy()
+        assert t.info()["num_segments"] == L
+        assert rel_fro(out, ref) <= TOL
+    t.close()
+
+
+def test_empty_tensor_gives_zero_output():
+    torch = pytest.importorskip("torch")
+    c = torch.zeros((3, 0), dtype=torch.int32, device="cuda")
+    v = torch.zeros(0, dtype=torch.float32, device="cuda")
+    t = alto.AltoTensor.build(c, v, (10, 20, 30))
+    fd = factors_dev(synth.factors(1, (10, 20, 30), 16))
+    out = torch.full((20, 16), 7.0, device="cuda")
+    t.mttkrp(fd, 1, out=out)
+    assert float(out.abs().max()) == 0.0
+    t.close()
+
+
+def test_invalid_calls():
+    rec = synth.Recipe("inv", (10, 20, 30), 100, (), seed=1)
+    coords, vals = synth.coo(rec)
+    c, v = to_dev(coords, vals)
+    t = alto.AltoTensor.build(c, v, rec.dims)
+    fd = factors_dev(synth.factors(1, rec.dims, 16))
+    with pytest.raises(ValueError):
+        t.mttkrp(fd, 3)
+    import ctypes
+    import torch
+    out = torch.zeros((30, 16), device="cuda")
+    fp = alto._ptr_array(fd)
+    L = alto.lib()
+    s = alto._stream()
+    assert L.alto_mttkrp(t._h, fp, 16, 0, 3, alto._ptr(out), None, s) == alto.E_INVAL   # mode >= N
+    assert L.alto_mttkrp(t._h, fp, 0, 0, 2, alto._ptr(out), None, s) == alto.E_INVAL   # R = 0
+    assert L.alto_mttkrp(t._h, fp, 257, 0, 2, alto._ptr(out), None, s) == alto.E_INVAL  # R > 256
+    assert L.alto_mttkrp(t._h, fp, 16, 7, 2, alto._ptr(out), None, s) == alto.E_INVAL   # precision
+    bad = alto._Exec(9, 0)
+    assert L.alto_mttkrp(t._h, fp, 16, 0, 2, alto._ptr(out), ctypes.byref(bad), s) == alto.E_INVAL
+    mis = ctypes.c_void_p(out.data_ptr() + 4)
+    assert L.alto_mttkrp(t._h, fp, 16, 0, 2, mis, None, s) == alto.E_INVAL             # misaligned output
+    t.close()
+
+
+def _hot_rows(col, dim, k):
+    cnt = np.bincount(col, minlength=dim)
+    return np.argsort(cnt)[::-1][:k]
+
+
+@pytest.mark.slow
+def test_full_size_sampled_rows():
+    """The benchmark tensor at full size (150M draws, 4 modes, R=32), in the
+    benchmark's launch configuration: every mode, sampled output rows
+    (hottest rows plus random ones) against the oracle computed row by row."""
+    rec = synth.WORKLOADS["zipf4_1Mx100kx10kx500_150M"]
+    coords, vals = synth.coo(rec)
+    c, v = to_dev(coords, vals)
+    t = alto.AltoTensor.build(c, v, rec.dims)
+    del c, v
+    fs = synth.factors(rec.seed + 1, rec.dims, rec.rank)
+    rng = np.random.default_rng(0)
+    for prec in ("f32", "bf16"):
+        fd = factors_dev(fs, prec)
+        for mode in range(4):
+            print("full-size mode", mode, prec, flush=True)
+            out = t.mttkrp(fd, mode).cpu().numpy()
+            rows = np.unique(np.concatenate([_hot_rows(coords[mode], rec.dims[mode], 8),
+                                             rng.integers(0, rec.dims[mode], 24)])).astype(np.uint32)
+            ref = oracle.mttkrp_rows(rec.dims, coords, vals, fs, mode, rows)
+            for q, r in enumerate(rows):
+                assert rel_fro(out[r], ref[q]) <= TOL, (mode, prec, int(r), rel_fro(out[r], ref[q]))
+    t.close()
