@@ -57,9 +57,14 @@ typedef enum {
 typedef enum {
     ALTO_STRATEGY_AUTO = 0,    /* selector network if loaded, else the reuse rule of Section 3.3 */
     ALTO_STRATEGY_ATOMIC = 1,  /* every partial result goes to the output with FP32 atomics */
-    ALTO_STRATEGY_STAGED = 2   /* per-segment partials in on-chip local memory over the segment's
+    ALTO_STRATEGY_STAGED = 2,  /* per-segment partials in on-chip local memory over the segment's
                                   mode interval, then merged into the output; segments whose
                                   interval does not fit fall back to atomics */
+    ALTO_STRATEGY_SORTED = 3   /* inside every line segment the nonzeros are taken in order of
+                                  their mode-n coordinate (a stable reordering built on first
+                                  use and kept per mode: one extra copy of index and values), so
+                                  each (segment, row) run is summed in registers and written
+                                  with one FP32 atomic per column */
 } alto_strategy;
 
 typedef struct alto_tensor alto_tensor;  /* opaque */
@@ -180,9 +185,10 @@ int alto_select(const alto_tensor *t, int mode, int R, int prec, alto_exec *out)
  * alto_selector_load — install selector weights (host floats, layout:
  * header {F = 12, H, K, nL} then feature mean[F], feature scale[F], the
  * training range fmin[F], fmax[F], the nL candidate segment counts,
- * W1[H*F], b1[H], W2[H*H], b2[H], W3[K*H], b3[K], with K = 2*nL outputs =
- * predicted log2 times of (atomic, L_0) .. (atomic, L_{nL-1}), (staged,
- * L_0) .. (staged, L_{nL-1})).  The network sees (feature - mean) / scale.
+ * W1[H*F], b1[H], W2[H*H], b2[H], W3[K*H], b3[K], with K = S*nL outputs
+ * (S = 2 or 3 strategies) = predicted log2 times of (atomic, L_0) ..
+ * (atomic, L_{nL-1}), (staged, L_0) .. (staged, L_{nL-1}), then (sorted,
+ * L_0) .. when S = 3.  The network sees (feature - mean) / scale.
  * n is the total float count; n == 0 unloads.
  */
 int alto_selector_load(const float *weights, size_t n);

@@ -20,7 +20,7 @@ MAX_MODES = 8
 
 OK, E_INVAL, E_TOO_WIDE, E_RANGE, E_NOMEM, E_HIP, E_NOTSPD, E_STATE = range(8)
 PREC = {"f32": 0, "bf16": 1}
-STRATEGY = {"auto": 0, "atomic": 1, "staged": 2}
+STRATEGY = {"auto": 0, "atomic": 1, "staged": 2, "sorted": 3}
 STRATEGY_NAME = {v: k for k, v in STRATEGY.items()}
 
 # Names the C ABI exports (include/alto.h).

@@ -101,6 +101,66 @@ void free_partition(alto_tensor *t) {
     p.h_ivl.clear();
     for (auto &kv : t->lists) (void)hipFree(kv.second.d);
     t->lists.clear();
+    for (int n = 0; n < kMaxModes; n++) {
+        (void)hipFree(t->okeys[n]);
+        (void)hipFree(t->ovals[n]);
+        t->okeys[n] = nullptr;
+        t->ovals[n] = nullptr;
+    }
+}
+
+// Segment-local order by one mode: inside every line segment, a stable
+// reordering of the nonzeros by their mode coordinate (radix sort of
+// (segment, row) keys carrying the position), then a gather of index and
+// values into their own arrays.  Built once per mode and partition.
+int build_mode_order(alto_tensor *t, int mode, hipStream_t s) {
+    if (t->okeys[mode]) return ALTO_OK;
+    const int64_t n = t->nnz;
+    const int L = t->part.L;
+    const int lbits = ceil_log2((uint64_t)std::max(1, L));
+    const int bits = lbits + t->nbits[mode];
+    const int wide = bits > 32;
+    const int okb = wide ? 64 : 32;
+    const size_t kb = (size_t)t->key_bits / 8;
+    void *ok = nullptr, *ok2 = nullptr;
+    uint32_t *pos = nullptr, *pos2 = nullptr;
+    int rc = ALTO_OK;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(ok);
+        (void)hipFree(ok2);
+        (void)hipFree(pos);
+        (void)hipFree(pos2);
+    };
+#define ALTO_TRY2(call)                             \
+    do {                                            \
+        hipError_t e_ = (call);                     \
+        if (e_ != hipSuccess) {                     \
+            rc = hip_error(e_, #call);              \
+            cleanup();                              \
+            return rc;                              \
+        }                                           \
+    } while (0)
+    ALTO_TRY2(hipMalloc(&ok, (size_t)n * okb / 8));
+    ALTO_TRY2(hipMalloc(&ok2, (size_t)n * okb / 8));
+    ALTO_TRY2(hipMalloc(&pos, (size_t)n * 4));
+    ALTO_TRY2(hipMalloc(&pos2, (size_t)n * 4));
+    rc = launch_order_keys(t->key_bits, t->keys, t->part.d_seg, L, t->tab, mode, t->nbits[mode], wide, ok, pos, s);
+    if (!rc) rc = ensure_workspace(t, radix_sort_scratch(okb, n));
+    bool in_alt = false;
+    if (!rc)
+        rc = radix_sort(okb, bits, n, ok, (float *)pos, ok2, (float *)pos2, t->ws, t->ws_bytes, &in_alt, s);
+    if (rc) {
+        cleanup();
+        return rc;
+    }
+    uint32_t *perm = in_alt ? pos2 : pos;
+    ALTO_TRY2(hipMalloc(&t->okeys[mode], kb * n));
+    ALTO_TRY2(hipMalloc(&t->ovals[mode], sizeof(float) * n));
+    rc = launch_gather(t->key_bits, t->keys, t->vals, perm, n, t->okeys[mode], t->ovals[mode], s);
+    cleanup();
+#undef ALTO_TRY2
+    return rc;
 }
 
 int cu_count() {
@@ -220,7 +280,7 @@ int ensure_workspace(alto_tensor *t, size_t bytes) {
 }
 
 int resolve_strategy(const alto_tensor *t, int mode, int R, int prec, const alto_exec *ex, alto_exec *res) {
-    if (ex && (ex->strategy < 0 || ex->strategy > 2)) return set_error(ALTO_E_INVAL, "unknown strategy");
+    if (ex && (ex->strategy < 0 || ex->strategy > 3)) return set_error(ALTO_E_INVAL, "unknown strategy");
     if (ex && ex->num_segments < 0) return set_error(ALTO_E_INVAL, "num_segments must be >= 0");
     if (ex && ex->strategy != ALTO_STRATEGY_AUTO) {
         *res = *ex;
@@ -259,8 +319,13 @@ int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int p
     const uint64_t outn = t->dims[mode] * (uint64_t)R;
     ALTO_HIP(hipMemsetAsync(out, 0, sizeof(float) * outn, s));
     if (t->nnz == 0) return ALTO_OK;
+    const bool sorted = plan.strategy == ALTO_STRATEGY_SORTED;
+    if (sorted) {
+        rc = build_mode_order(t, mode, s);
+        if (rc) return rc;
+    }
     SegLists *sl = nullptr;
-    rc = build_lists(t, mode, plan.strategy, R, prec, &sl);
+    rc = build_lists(t, mode, sorted ? ALTO_STRATEGY_ATOMIC : plan.strategy, R, prec, &sl);
     if (rc) return rc;
     // per-XCD replicas for the atomic updates when they are cheap next to the
     // nonzero traffic (ALTO_REPLICAS=0/1 forces the choice)
@@ -279,8 +344,8 @@ int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int p
     }
     if (use_rep) ALTO_HIP(hipMemsetAsync(t->rep, 0, rep_bytes, s));
     MtLaunch a{};
-    a.keys = t->keys;
-    a.vals = t->vals;
+    a.keys = sorted ? t->okeys[mode] : t->keys;
+    a.vals = sorted ? t->ovals[mode] : t->vals;
     a.seg = t->part.d_seg;
     a.ivl = t->part.d_ivl;
     a.cov = t->part.d_cov[mode];

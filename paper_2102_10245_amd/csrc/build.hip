@@ -382,6 +382,31 @@ __global__ __launch_bounds__(kThreads) void intervals_k(const K *__restrict__ ke
     }
 }
 
+// ------------------------------------------------------------ mode ordering
+// okey[x] = (segment of x) << shift | row of x along `mode`; pos[x] = x.
+template <typename K, typename OK>
+__global__ __launch_bounds__(kThreads) void order_keys_k(const K *__restrict__ keys, const int64_t *__restrict__ seg,
+                                                         RunTable tab, int mode, int shift, OK *__restrict__ okey,
+                                                         uint32_t *__restrict__ pos) {
+    const int l = blockIdx.x;
+    const int64_t b = seg[l], e = seg[l + 1];
+    for (int64_t x = b + threadIdx.x; x < e; x += kThreads) {
+        okey[x] = ((OK)l << shift) | (OK)extract_mode(keys[x], tab, mode);
+        pos[x] = (uint32_t)x;
+    }
+}
+
+template <typename K>
+__global__ __launch_bounds__(kThreads) void gather_k(const K *__restrict__ keys, const float *__restrict__ vals,
+                                                     const uint32_t *__restrict__ pos, int64_t n, K *__restrict__ okeys,
+                                                     float *__restrict__ ovals) {
+    for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < n; x += (int64_t)gridDim.x * kThreads) {
+        const uint32_t p = pos[x];
+        okeys[x] = keys[p];
+        ovals[x] = vals[p];
+    }
+}
+
 // ------------------------------------------------------------ coverage
 __global__ __launch_bounds__(kThreads) void coverage_marks_k(const uint32_t *__restrict__ ivl, int L, int N, int mode,
                                                              int32_t *__restrict__ diff) {
@@ -520,6 +545,34 @@ int coverage(int N, int L, const uint32_t *d_ivl, int mode, uint64_t dim, uint32
         ALTO_HIP(hipGetLastError());
     }
     return device_scan<int32_t, int32_t, true>(diff, (int32_t *)cov, (int64_t)dim, nullptr, scan_ws, s);
+}
+
+int launch_order_keys(int key_bits, const void *keys, const int64_t *seg, int L, const RunTable &tab, int mode,
+                      int shift, int wide, void *okey, uint32_t *pos, hipStream_t s) {
+    if (L <= 0) return ALTO_OK;
+#define ALTO_OK_(K, OK) \
+    order_keys_k<K, OK><<<L, kThreads, 0, s>>>((const K *)keys, seg, tab, mode, shift, (OK *)okey, pos)
+    if (key_bits == 32) {
+        if (wide) ALTO_OK_(uint32_t, uint64_t); else ALTO_OK_(uint32_t, uint32_t);
+    } else if (key_bits == 64) {
+        if (wide) ALTO_OK_(uint64_t, uint64_t); else ALTO_OK_(uint64_t, uint32_t);
+    } else {
+        if (wide) ALTO_OK_(u128, uint64_t); else ALTO_OK_(u128, uint32_t);
+    }
+#undef ALTO_OK_
+    ALTO_HIP(hipGetLastError());
+    return ALTO_OK;
+}
+
+int launch_gather(int key_bits, const void *keys, const float *vals, const uint32_t *pos, int64_t n, void *okeys,
+                  float *ovals, hipStream_t s) {
+    if (n <= 0) return ALTO_OK;
+    const unsigned g = grid_for(n, kThreads * 4);
+    if (key_bits == 32) gather_k<uint32_t><<<g, kThreads, 0, s>>>((const uint32_t *)keys, vals, pos, n, (uint32_t *)okeys, ovals);
+    else if (key_bits == 64) gather_k<uint64_t><<<g, kThreads, 0, s>>>((const uint64_t *)keys, vals, pos, n, (uint64_t *)okeys, ovals);
+    else gather_k<u128><<<g, kThreads, 0, s>>>((const u128 *)keys, vals, pos, n, (u128 *)okeys, ovals);
+    ALTO_HIP(hipGetLastError());
+    return ALTO_OK;
 }
 
 int launch_sumsq(const float *vals, int64_t n, double *out, hipStream_t s) {

@@ -17,12 +17,14 @@
 // A flush goes either to Temp (Algorithm 2, local staging: LDS rows
 // [T^s, T^e] of the segment's mode interval, merged into the output when the
 // segment is done: plain stores for rows no other segment covers, FP32 atomics
-// otherwise) or straight out with FP32 atomics (Algorithm 2, atomic update).
-// Atomic updates can target a per-XCD replica of the output (chosen by the
-// XCC id register) so that the lines a replica owns are only ever touched by
-// one L2; a reduction adds the replicas into the output afterwards.  The
-// atomics are device-scope either way, so the result does not depend on which
-// XCD a workgroup runs on.
+// otherwise) or out with FP32 atomics (Algorithm 2, atomic update).  Atomic
+// flushes are queued in LDS and drained by the whole wave with R consecutive
+// lanes per output row, so each atomic instruction covers whole 128-byte
+// lines (on this GPU global atomics cost per line touched).  They can target
+// a per-XCD replica of the output (chosen by the XCC id register) so that the
+// lines a replica owns are only ever touched by one L2; a reduction adds the
+// replicas into the output afterwards.  The atomics are device-scope either
+// way, so the result does not depend on which XCD a workgroup runs on.
 #pragma once
 
 #include "common.h"
@@ -84,11 +86,21 @@ struct MtCfg {
     static constexpr int kGPW = 64 / kG;                      // lane groups per wave
     static constexpr int kCols = RT ? 1 : 4;                  // column chunks per lane (generic rank)
     static constexpr int kNMax = NT ? NT : kMaxModes;
-    static constexpr int kU = (NT == 0 || RT == 0) ? 1 : (kG >= 2 ? 2 : 1);  // nonzeros in flight per group
+    static constexpr int kU = kG >= 4 ? 4 : kG;               // nonzeros in flight per group
+    // flush queue (rank-specialized atomic path): rows per wave
+    static constexpr bool kQueue = RT != 0 && RT <= 64;
+    static constexpr int kQRows = kQueue ? 4 * kGPW : 0;      // a tile of U items flushes at most U rows per group
 };
 
 // LDS row stride of Temp: one float of padding spreads rows over the banks.
 __host__ __device__ inline int temp_stride(int R) { return R + 1; }
+
+// LDS bytes of the per-wave flush queues of one workgroup.
+template <int NT, int RT, typename FT>
+__host__ __device__ constexpr int mt_queue_bytes(int threads) {
+    using C = MtCfg<NT, RT, FT>;
+    return C::kQueue ? (threads / 64) * C::kQRows * (RT + 1) * 4 : 0;
+}
 
 __device__ __forceinline__ uint32_t xcc_id() {
     // hwreg(HW_REG_XCC_ID, 0, 4): id 20, offset 0, 4 bits
@@ -103,9 +115,11 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
     const int32_t *__restrict__ seg_list, int n_list) {
     using C = MtCfg<NT, RT, FT>;
     constexpr int VEC = C::kVec, G = C::kG, GPW = C::kGPW, NM = C::kNMax, NCOL = C::kCols, U = C::kU;
+    constexpr bool QUEUE = C::kQueue && !kStaged;
+    constexpr int QR = C::kQRows;
     const int N = NT ? NT : N_rt;
     const int R = RT ? RT : R_rt;
-    extern __shared__ float temp[];
+    extern __shared__ float smem[];
 
     // XCD-aware order: consecutive list entries (neighbouring segments, which
     // touch neighbouring factor rows) go to the same L2.
@@ -126,6 +140,9 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
 
     float *const atom = rep ? rep + (uint64_t)(xcc_id() % (uint32_t)nrep) * rep_stride : out;
     const int RP = temp_stride(R);
+    float *const temp = smem;                                      // staged: Temp rows
+    float *const qbuf = smem + (QUEUE ? wave * QR * (RT + 1) : 0);  // atomic: this wave's flush queue
+    int qn = 0;                                                    // queued rows (wave-uniform)
 
     uint32_t lo = 0, width = 0;
     if constexpr (kStaged) {
@@ -142,7 +159,8 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
 #pragma unroll
         for (int e = 0; e < VEC; e++) acc[a][e] = 0.f;
 
-    auto flush = [&](uint32_t row, const float (&v)[NCOL][VEC]) {
+    // direct flush: LDS Temp (staged) or global atomics (generic rank)
+    auto flush_direct = [&](uint32_t row) {
 #pragma unroll
         for (int a = 0; a < NCOL; a++) {
             const int col0 = RT ? c * VEC : c + 64 * a;
@@ -150,23 +168,30 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
             if constexpr (kStaged) {
                 float *dst = temp + (uint64_t)(row - lo) * RP + col0;
 #pragma unroll
-                for (int e = 0; e < VEC; e++) atomicAdd(dst + e, v[a][e]);
+                for (int e = 0; e < VEC; e++) atomicAdd(dst + e, acc[a][e]);
             } else {
                 float *dst = atom + (uint64_t)row * R + col0;
 #pragma unroll
-                for (int e = 0; e < VEC; e++) unsafeAtomicAdd(dst + e, v[a][e]);
+                for (int e = 0; e < VEC; e++) unsafeAtomicAdd(dst + e, acc[a][e]);
             }
         }
     };
 
-    // Flushes found while combining a batch are issued only after the next
-    // batch's gathers, so that waiting for those loads does not also wait for
-    // the atomics (loads and atomics share one in-order memory counter).
-    bool pend[U];
-    uint32_t prow[U];
-    float pacc[U][NCOL][VEC];
-#pragma unroll
-    for (int u = 0; u < U; u++) pend[u] = false;
+    // The whole wave empties the queue: R consecutive lanes per queued row.
+    auto drain = [&]() {
+        if constexpr (QUEUE) {
+            constexpr int PER = 64 / RT;  // rows per instruction
+            for (int q0 = 0; q0 < qn; q0 += PER) {
+                const int q = q0 + lane / RT, col = lane % RT;
+                if (q < qn) {
+                    const float *e = qbuf + q * (RT + 1);
+                    const uint32_t row = __float_as_uint(e[RT]);
+                    unsafeAtomicAdd(atom + (uint64_t)row * RT + col, e[col]);
+                }
+            }
+            qn = 0;
+        }
+    };
 
     // prefetch the first tile: lane c of group g owns items gb + t*G + c
     int64_t pos = gb + c;
@@ -195,81 +220,89 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
 
         for (int k0 = 0; k0 < G; k0 += U) {
             uint32_t rows[U];
-            float vv[U];
-            float f[U][NM][NCOL][VEC];
-            // (1) gathers of this batch
+            float p[U][NCOL][VEC];
 #pragma unroll
             for (int u = 0; u < U; u++) {
                 const int src = gw * G + k0 + u;
-                rows[u] = G == 1 ? myrow : (uint32_t)__shfl((int)myrow, src);
-                vv[u] = G == 1 ? v : __shfl(v, src);
+                const uint32_t row = G == 1 ? myrow : (uint32_t)__shfl((int)myrow, src);
+                const float vv = G == 1 ? v : __shfl(v, src);
+                rows[u] = row;
+#pragma unroll
+                for (int a = 0; a < NCOL; a++)
+#pragma unroll
+                    for (int e = 0; e < VEC; e++) p[u][a][e] = vv;
 #pragma unroll
                 for (int m = 0; m < NM; m++) {
                     if (m >= N || m == mode) continue;
                     const uint32_t im = G == 1 ? idx[m] : (uint32_t)__shfl((int)idx[m], src);
                     const uint64_t rowoff = (uint64_t)im * (uint64_t)R;
                     if constexpr (RT != 0) {
-                        FactorLoad<FT>::load(fac.p[m], rowoff + (uint64_t)c * VEC, f[u][m][0]);
+                        float f[VEC];
+                        FactorLoad<FT>::load(fac.p[m], rowoff + (uint64_t)c * VEC, f);
+#pragma unroll
+                        for (int e = 0; e < VEC; e++) p[u][0][e] *= f[e];
                     } else {
 #pragma unroll
                         for (int a = 0; a < NCOL; a++) {
                             const int col = c + 64 * a;
-                            f[u][m][a][0] = col < R ? FactorLoad<FT>::load1(fac.p[m], rowoff + col) : 0.f;
+                            const float f = col < R ? FactorLoad<FT>::load1(fac.p[m], rowoff + col) : 0.f;
+                            p[u][a][0] *= f;
                         }
                     }
                 }
             }
-            // (2) the previous batch's flushes
-#pragma unroll
-            for (int u = 0; u < U; u++)
-                if (pend[u]) {
-                    flush(prow[u], pacc[u]);
-                    pend[u] = false;
-                }
-            // (3) products and run combining
 #pragma unroll
             for (int u = 0; u < U; u++) {
-                if (rows[u] == kNoRow) continue;
-                float p[NCOL][VEC];
+                const bool valid = rows[u] != kNoRow;
+                const bool brk = valid && rows[u] != cur && cur != kNoRow;
+                if constexpr (QUEUE) {
+                    // groups whose run ends append (row, accumulator) to the wave's queue
+                    const uint64_t fl = __ballot(brk && c == 0);
+                    if (brk) {
+                        const int slot = qn + __builtin_popcountll(fl & ((1ull << (gw * G)) - 1ull));
+                        float *e = qbuf + slot * (RT + 1);
 #pragma unroll
-                for (int a = 0; a < NCOL; a++)
-#pragma unroll
-                    for (int e = 0; e < VEC; e++) p[a][e] = vv[u];
-#pragma unroll
-                for (int m = 0; m < NM; m++) {
-                    if (m >= N || m == mode) continue;
-#pragma unroll
-                    for (int a = 0; a < NCOL; a++)
-#pragma unroll
-                        for (int e = 0; e < VEC; e++) p[a][e] *= f[u][m][a][e];
+                        for (int q = 0; q < VEC; q++) e[c * VEC + q] = acc[0][q];
+                        if (c == 0) e[RT] = __uint_as_float(cur);
+                    }
+                    qn += __builtin_popcountll(fl);
+                } else {
+                    if (brk) flush_direct(cur);
                 }
-                if (rows[u] != cur) {
-                    if (cur != kNoRow) {
-                        pend[u] = true;
-                        prow[u] = cur;
+                if (valid) {
+                    if (rows[u] != cur) {
+                        cur = rows[u];
 #pragma unroll
                         for (int a = 0; a < NCOL; a++)
 #pragma unroll
-                            for (int e = 0; e < VEC; e++) pacc[u][a][e] = acc[a][e];
+                            for (int e = 0; e < VEC; e++) acc[a][e] = p[u][a][e];
+                    } else {
+#pragma unroll
+                        for (int a = 0; a < NCOL; a++)
+#pragma unroll
+                            for (int e = 0; e < VEC; e++) acc[a][e] += p[u][a][e];
                     }
-                    cur = rows[u];
-#pragma unroll
-                    for (int a = 0; a < NCOL; a++)
-#pragma unroll
-                        for (int e = 0; e < VEC; e++) acc[a][e] = p[a][e];
-                } else {
-#pragma unroll
-                    for (int a = 0; a < NCOL; a++)
-#pragma unroll
-                        for (int e = 0; e < VEC; e++) acc[a][e] += p[a][e];
                 }
+            }
+            if constexpr (QUEUE) {
+                if (qn > QR - U * GPW) drain();
             }
         }
     }
+    if constexpr (QUEUE) {
+        const uint64_t fl = __ballot(cur != kNoRow && c == 0);
+        if (cur != kNoRow) {
+            const int slot = qn + __builtin_popcountll(fl & ((1ull << (gw * G)) - 1ull));
+            float *e = qbuf + slot * (RT + 1);
 #pragma unroll
-    for (int u = 0; u < U; u++)
-        if (pend[u]) flush(prow[u], pacc[u]);
-    if (cur != kNoRow) flush(cur, acc);
+            for (int q = 0; q < VEC; q++) e[c * VEC + q] = acc[0][q];
+            if (c == 0) e[RT] = __uint_as_float(cur);
+        }
+        qn += __builtin_popcountll(fl);
+        drain();
+    } else {
+        if (cur != kNoRow) flush_direct(cur);
+    }
     if constexpr (kStaged) {
         // merge Temp into the output (the pull of Algorithm 2 for this segment)
         __syncthreads();
@@ -308,7 +341,8 @@ struct MtLaunch {
 template <typename K, int NT, int RT, typename FT>
 int launch_mt_cfg(const MtLaunch &a, hipStream_t s) {
     if (a.n_list <= 0) return ALTO_OK;
-    const size_t lds = a.staged ? (size_t)a.temp_rows * temp_stride(a.R) * 4 : 0;
+    const size_t lds = a.staged ? (size_t)a.temp_rows * temp_stride(a.R) * 4
+                                : (size_t)mt_queue_bytes<NT, RT, FT>(a.threads);
     const int per = (a.n_list + 7) / 8;
     const unsigned grid = (unsigned)per * 8;
     auto kern = a.staged ? mttkrp_k<K, NT, RT, FT, true> : mttkrp_k<K, NT, RT, FT, false>;

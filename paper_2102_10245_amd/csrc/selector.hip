@@ -83,8 +83,8 @@ int alto_selector_load(const float *w, size_t n) {
     s.H = (int)w[1];
     s.K = (int)w[2];
     s.nL = (int)w[3];
-    if (s.F != kF || s.H < 1 || s.H > 256 || s.nL < 1 || s.K != 2 * s.nL)
-        return set_error(ALTO_E_INVAL, "selector header must be {12, H<=256, 2*nL, nL}");
+    if (s.F != kF || s.H < 1 || s.H > 256 || s.nL < 1 || (s.K != 2 * s.nL && s.K != 3 * s.nL))
+        return set_error(ALTO_E_INVAL, "selector header must be {12, H<=256, 2*nL or 3*nL, nL}");
     const size_t need = 4 + 4 * (size_t)s.F + s.nL + (size_t)s.H * s.F + s.H + (size_t)s.H * s.H + s.H +
                         (size_t)s.K * s.H + s.K;
     if (n != need) return set_error(ALTO_E_INVAL, "selector weight count does not match its header");
@@ -152,7 +152,8 @@ int alto_select(const alto_tensor *t, int mode, int R, int prec, alto_exec *out)
             best = k;
         }
     }
-    out->strategy = best < s.nL ? ALTO_STRATEGY_ATOMIC : ALTO_STRATEGY_STAGED;
+    static const int order[3] = {ALTO_STRATEGY_ATOMIC, ALTO_STRATEGY_STAGED, ALTO_STRATEGY_SORTED};
+    out->strategy = order[best / s.nL];
     out->num_segments = (int)s.Ls[best % s.nL];
     return ALTO_OK;
 }

@@ -28,7 +28,7 @@ CASES = [
 ]
 
 
-def _run_case(rec, R, L, strategies=("atomic", "staged", "auto"), precs=("f32", "bf16")):
+def _run_case(rec, R, L, strategies=("atomic", "staged", "sorted", "auto"), precs=("f32", "bf16")):
     coords, vals = synth.coo(rec)
     c, v = to_dev(coords, vals)
     t = alto.AltoTensor.build(c, v, rec.dims, num_segments=L)
@@ -66,9 +66,10 @@ def test_repartition_through_exec():
     fd = factors_dev(fs)
     ref = oracle.mttkrp(rec.dims, coords, vals, fs, 1)
     for L in (128, 4096, 7):
-        out = t.mttkrp(fd, 1, strategy="staged", num_segments=L).cpu().numpy()
-        assert t.info()["num_segments"] == L
-        assert rel_fro(out, ref) <= TOL
+        for st in ("staged", "sorted"):
+            out = t.mttkrp(fd, 1, strategy=st, num_segments=L).cpu().numpy()
+            assert t.info()["num_segments"] == L
+            assert rel_fro(out, ref) <= TOL
     t.close()
 
 
