@@ -1,17 +1,20 @@
 """Benchmark: ALTO sparse MTTKRP / CP-ALS on one MI355X.
 
-One step = the whole hot path over one synthetic tensor, inputs already in
-HBM: alto_build (linearize, radix-sort, coalesce, partition, intervals,
-coverage) followed by CP-ALS (per mode: strategy choice, MTTKRP, merge,
-FP64 normal equations) for the configured number of iterations.
+One step = the whole hot path over one synthetic tensor whose COO input is
+already in HBM: alto_build (linearize, radix-sort, coalesce, partition,
+intervals, coverage) followed by CP-ALS for the configured number of
+iterations (per mode: execution choice, MTTKRP, merge, FP64 normal
+equations), FP32 factors, execution chosen by the library (the trained
+selector network when its weights are present, else the reuse rule).
 
 value = MTTKRP nonzeros processed per second over the whole step
         (iterations x modes x distinct nonzeros / step time).
 
-Extra fields: per-mode MTTKRP nnz/s, logical GB/s and % of the 8 TB/s HBM
-peak (FP32 and BF16 factors), CP-ALS ms per iteration (FP32 vs BF16),
-build time, fits; `roofline` for the MTTKRP kernel; `cpu_baseline` (the
-FP64 oracle on a bounded sample, one host core).
+Extra fields: per-mode MTTKRP time, nnz/s and % of the 8 TB/s HBM peak in
+algorithmic bytes for every strategy, FP32 and BF16 factors; CP-ALS ms per
+iteration and fit for the plain FP32 form (reuse rule, no network) and the
+network-chosen FP32 and BF16 forms; `roofline` for the MTTKRP kernel;
+`cpu_baseline` (the FP64 oracle on a bounded sample, one host core).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -38,11 +41,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="zipf4_1Mx100kx10kx500_150M")
     ap.add_argument("--iters", type=int, default=20, help="CP-ALS iterations per step")
-    ap.add_argument("--reps", type=int, default=20, help="timed repetitions per mode for per-mode MTTKRP")
+    ap.add_argument("--reps", type=int, default=10, help="timed repetitions per mode for per-mode MTTKRP")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-selector", action="store_true", help="do not load the selector weights")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle CPU time")
     ap.add_argument("--mttkrp-only", action="store_true",
-                    help="only the per-mode MTTKRP repetitions (for counter collection)")
+                    help="only per-mode MTTKRP repetitions of the chosen plan (for counter collection)")
     return ap.parse_args()
 
 
@@ -68,46 +72,55 @@ def main():
     alto.lib()  # fail loudly if the HIP library is missing
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    have_sel = (not args.no_selector) and alto.load_default_selector()
     rec = synth.WORKLOADS[args.workload]
     R = rec.rank
     t0 = time.time()
     coords, vals = synth.coo(rec)
-    print(f"[bench] generated {rec.name}: {coords.shape[1]} draws in {time.time() - t0:.1f}s", file=sys.stderr,
-          flush=True)
+    log(f"generated {rec.name}: {coords.shape[1]} draws in {time.time() - t0:.1f}s; selector "
+        f"{'loaded' if have_sel else 'absent (reuse rule)'}")
     c_dev = torch.from_numpy(coords.view(np.int32)).to(dev)
     v_dev = torch.from_numpy(vals).to(dev)
     init = synth.factors(rec.seed + 1, rec.dims, R)
     init_f32 = [torch.from_numpy(f).to(dev) for f in init]
     init_bf16 = [f.to(torch.bfloat16) for f in init_f32]
-    work_f32 = [f.clone() for f in init_f32]
-    work_bf16 = [f.clone() for f in init_bf16]
+    work = {"f32": [f.clone() for f in init_f32], "bf16": [f.clone() for f in init_bf16]}
+    src = {"f32": init_f32, "bf16": init_bf16}
     N = len(rec.dims)
     torch.cuda.synchronize()
 
     def step(prec="f32", timers=None):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)] if timers is not None else None
-        work = work_f32 if prec == "f32" else work_bf16
-        src = init_f32 if prec == "f32" else init_bf16
-        for w, s in zip(work, src):
+        for w, s in zip(work[prec], src[prec]):
             w.copy_(s)
         if ev:
             ev[0].record()
         t = alto.AltoTensor.build(c_dev, v_dev, rec.dims)
         if ev:
             ev[1].record()
-        lam, fit = t.cp_als(work, args.iters)
+        lam, fit = t.cp_als(work[prec], args.iters)
         if ev:
             ev[2].record()
         info = t.info()
+        plan = [t.select(m, R, prec) for m in range(N)]
         t.close()
         if timers is not None:
             torch.cuda.synchronize()
             timers.append((ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])))
-        return info, fit
+        return info, fit, plan
 
     if args.mttkrp_only:
+        # a plain 1 GiB device copy first: its counter readings calibrate the
+        # HBM byte counters (FETCH_SIZE / WRITE_SIZE) against a known size
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
         t = alto.AltoTensor.build(c_dev, v_dev, rec.dims)
-        per_mode = time_modes(alto, torch, t, init_f32, R, N, args.reps, "f32")
+        per_mode = time_modes(alto, torch, t, init_f32, R, N, args.reps, "f32", "auto")
         print(json.dumps({"mttkrp_only": per_mode}))
         t.close()
         return
@@ -117,35 +130,49 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
-    for _ in range(args.steps):
+    for k in range(args.steps):
         infos.append(step())
+        log(f"step {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    info, fit_f32 = infos[-1]
+    info, fit_f32, plan_f32 = infos[-1]
     M = info["nnz"]
     ms_per_step = 1e3 * elapsed / args.steps
     value = args.iters * N * M / (elapsed / args.steps)
 
-    # build / CP-ALS split (FP32 and BF16 factors), event-timed
-    tim_f32, tim_bf16 = [], []
-    step("f32", tim_f32)
-    _, fit_bf16 = step("bf16", tim_bf16)
+    # the forms: network-chosen FP32 / BF16, and the plain FP32 form (reuse rule)
+    forms = {}
+    for name, prec, sel in (("selector_f32", "f32", have_sel), ("selector_bf16", "bf16", have_sel),
+                            ("plain_f32", "f32", False)):
+        if not sel:
+            alto.selector_load(None)
+        tim = []
+        _, fit, plan = step(prec, tim)
+        if have_sel:
+            alto.load_default_selector()
+        forms[name] = {"build_ms": tim[0][0], "cp_als_ms_per_iter": tim[0][1] / args.iters,
+                       "fit": float(fit[-1]) if len(fit) else None,
+                       "plan": [{"strategy": s, "num_segments": L} for s, L in plan]}
+        log(f"{name}: CP-ALS {tim[0][1] / args.iters:.2f} ms/iter, fit {forms[name]['fit']:.6f}, plan {plan}")
 
-    # per-mode MTTKRP on the built tensor
+    # per-mode MTTKRP for every strategy and precision on the built tensor
     t = alto.AltoTensor.build(c_dev, v_dev, rec.dims)
-    per_f32 = time_modes(alto, torch, t, init_f32, R, N, args.reps, "f32")
-    per_bf16 = time_modes(alto, torch, t, init_bf16, R, N, args.reps, "bf16")
+    per_mode = {}
+    for prec, fs in (("f32", init_f32), ("bf16", init_bf16)):
+        for st in ("auto", "atomic", "staged", "sorted"):
+            per_mode[f"{st}_{prec}"] = time_modes(alto, torch, t, fs, R, N, args.reps, prec, st)
     kb = t.info()["key_bits"]
     t.close()
 
-    # roofline of the MTTKRP (the dominant kernel): algorithmic bytes per
-    # launch over the mean launch time, all modes pooled
-    tot_bytes = sum(m["logical_bytes"] for m in per_f32)
-    tot_ms = sum(m["ms"] for m in per_f32)
+    # roofline of the MTTKRP kernel under the chosen FP32 plan: algorithmic
+    # bytes per launch over the mean launch time (all modes pooled)
+    main_modes = per_mode["auto_f32"]
+    tot_bytes = sum(m["logical_bytes"] for m in main_modes)
+    tot_ms = sum(m["ms"] for m in main_modes)
     achieved = tot_bytes / (tot_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "mttkrp_k (FP32 factors, all modes, mean per launch)"}
+                "kernel": "mttkrp_k (64-bit index, order 4, R=32, FP32 factors), mean over the 4 modes"}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -168,43 +195,44 @@ def main():
             "workload": rec.name, "dims": list(rec.dims), "nnz_draws": rec.nnz, "nnz": M,
             "zipf": list(rec.zipf), "values": rec.values, "rank": R, "cp_als_iters": args.iters,
             "index_bits": info["index_bits"], "key_bits": kb, "num_segments": info["num_segments"],
-            "parallelism": "single GPU",
+            "execution": "selector" if have_sel else "reuse rule",
+            "plan": [{"strategy": s, "num_segments": L} for s, L in plan_f32],
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "per_mode_f32": per_f32,
-        "per_mode_bf16": per_bf16,
-        "build_ms": float(np.mean([a for a, _ in tim_f32])),
-        "cp_als_ms_per_iter_f32": float(np.mean([b for _, b in tim_f32])) / args.iters,
-        "cp_als_ms_per_iter_bf16": float(np.mean([b for _, b in tim_bf16])) / args.iters,
+        "forms": forms,
+        "per_mode": per_mode,
         "fit_f32": float(fit_f32[-1]) if len(fit_f32) else None,
-        "fit_bf16": float(fit_bf16[-1]) if len(fit_bf16) else None,
     }
     print(json.dumps(out))
 
 
-def time_modes(alto, torch, t, factors, R, N, reps, prec):
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def time_modes(alto, torch, t, factors, R, N, reps, prec, strategy):
     info = t.info()
     M = info["nnz"]
     fb = 4 if prec == "f32" else 2
     res = []
     for mode in range(N):
         out = torch.empty((info["dims"][mode], R), dtype=torch.float32, device=factors[0].device)
-        strat, L = t.select(mode, R, prec)
-        t.mttkrp(factors, mode, out=out)  # warmup (plans the segment lists)
+        strat, L = t.select(mode, R, prec) if strategy == "auto" else (strategy, 0)
+        t.mttkrp(factors, mode, out=out, strategy=strategy)  # warmup (plans, orders)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(reps):
-            t.mttkrp(factors, mode, out=out)
+            t.mttkrp(factors, mode, out=out, strategy=strategy)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
         lb = logical_bytes_per_nnz(N, R, info["key_bits"], fb) * M
-        res.append({"mode": mode, "strategy": strat, "ms": ms, "nnz_per_s": M / (ms * 1e-3),
-                    "logical_bytes": lb, "logical_GBps": lb / (ms * 1e-3) / 1e9,
+        res.append({"mode": mode, "strategy": strat, "num_segments": L or info["num_segments"], "ms": ms,
+                    "nnz_per_s": M / (ms * 1e-3), "logical_bytes": lb, "logical_GBps": lb / (ms * 1e-3) / 1e9,
                     "pct_hbm_peak": 100.0 * lb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS})
-        print(f"[bench] mode {mode} {prec} {strat}: {ms:.3f} ms, {M / (ms * 1e-3) / 1e9:.2f} G nnz/s, "
-              f"{res[-1]['pct_hbm_peak']:.1f}% of HBM peak (logical bytes)", file=sys.stderr, flush=True)
+        log(f"mode {mode} {prec} {strategy}->{strat}: {ms:.3f} ms, {M / (ms * 1e-3) / 1e9:.2f} G nnz/s, "
+            f"{res[-1]['pct_hbm_peak']:.1f}% of HBM peak (algorithmic bytes)")
     return res
 
 
@@ -214,13 +242,12 @@ def cpu_baseline(rec, coords, vals, init, R, N, seconds):
     import oracle
     oracle.build(force=False)
     init = [np.asarray(f, np.float64) for f in init]
-    s = 20000
+    s = 200000
     t0 = time.perf_counter()
     for mode in range(N):
         oracle.mttkrp(rec.dims, coords[:, :s], vals[:s], init, mode)
     dt = time.perf_counter() - t0
-    per_nnz_mode = dt / (s * N)
-    s = int(min(coords.shape[1], max(s, seconds / max(per_nnz_mode * N, 1e-12))))
+    s = int(min(coords.shape[1], max(s, s * seconds / max(dt, 1e-9))))
     t0 = time.perf_counter()
     for mode in range(N):
         oracle.mttkrp(rec.dims, coords[:, :s], vals[:s], init, mode)

@@ -123,14 +123,21 @@ int alto_build(const uint32_t *const *coords, const float *vals, int64_t nnz,
                const uint64_t *dims, int N, const alto_opts *opts, alto_tensor **out,
                hipStream_t stream);
 
+/* alto_layout — the bit layout alto_build uses for these mode lengths
+ * (Section 3.1), without building anything: fills N, index_bits, key_bits,
+ * dims, mode_bits, mask_lo and mask_hi of *out (other fields zero).
+ * key_bits as in alto_opts.  Host only; needs no GPU. */
+int alto_layout(const uint64_t *dims, int N, int key_bits, alto_info_t *out);
+
 /* alto_info — fill *out (host) with the tensor's description.  No device work. */
 int alto_info(const alto_tensor *t, alto_info_t *out);
 
 /*
- * alto_partition — re-cut the ordered tensor into L equal-nonzero segments
- * (Section 3.2): segment l holds positions [floor(l*nnz/L), floor((l+1)*nnz/L)),
- * L capped at nnz.  Recomputes the mode intervals and per-row coverage.
- * Synchronizes the stream once.
+ * alto_partition — make the cut of the ordered tensor into L equal-nonzero
+ * segments (Section 3.2) current: segment l holds positions
+ * [floor(l*nnz/L), floor((l+1)*nnz/L)), L capped at nnz, with its mode
+ * intervals and per-row coverage.  A partition built earlier (the last four
+ * are kept) is reused; building one synchronizes the stream once.
  */
 int alto_partition(alto_tensor *t, int num_segments, hipStream_t stream);
 
@@ -145,8 +152,10 @@ int alto_partition(alto_tensor *t, int num_segments, hipStream_t stream);
  *   out      device, I_mode x R floats; overwritten (rows with no nonzero
  *            become 0).
  *   ex       may be NULL (AUTO, current partition).  If ex->num_segments
- *            differs from the current L the tensor is re-partitioned first
- *            (that re-partition synchronizes the stream).
+ *            (or the selector's choice) differs from the current L, the
+ *            partition into that many segments becomes the current one; it
+ *            is built on first use (which synchronizes the stream) and kept,
+ *            with up to three other recent partitions, for later calls.
  * Asynchronous otherwise.  FP32 accumulation; atomics make the summation
  * order, hence the last bits, run-dependent.
  */

@@ -28,7 +28,7 @@ EXPORTS = (
     "alto_build", "alto_info", "alto_partition", "alto_mttkrp", "cp_als", "alto_select",
     "alto_selector_load", "alto_selector_features", "alto_mlp_forward", "alto_mlp_backward",
     "alto_mlp_adam", "alto_export_keys", "alto_export_partition", "alto_export_coverage",
-    "alto_round_bf16", "alto_free", "alto_last_error", "alto_device_compute_units",
+    "alto_round_bf16", "alto_free", "alto_last_error", "alto_device_compute_units", "alto_layout",
 )
 
 
@@ -75,6 +75,7 @@ def lib():
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
     L.alto_build.argtypes = [vp, vp, i64, vp, i32, vp, ctypes.POINTER(vp), vp]
     L.alto_info.argtypes = [vp, ctypes.POINTER(_Info)]
+    L.alto_layout.argtypes = [vp, i32, i32, ctypes.POINTER(_Info)]
     L.alto_partition.argtypes = [vp, i32, vp]
     L.alto_mttkrp.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp]
     L.cp_als.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp]
@@ -293,6 +294,17 @@ class AltoTensor:
         return cov
 
 
+def layout(dims, key_bits: int = 0) -> dict:
+    """The library's bit layout for these mode lengths (host only)."""
+    N = len(dims)
+    d = (ctypes.c_uint64 * N)(*[int(x) for x in dims])
+    inf = _Info()
+    _check(lib().alto_layout(d, N, key_bits, ctypes.byref(inf)))
+    return {"N": N, "index_bits": inf.index_bits, "key_bits": inf.key_bits,
+            "mode_bits": [int(inf.mode_bits[n]) for n in range(N)],
+            "masks": [int(inf.mask_lo[n]) | (int(inf.mask_hi[n]) << 64) for n in range(N)]}
+
+
 def build_tensor(coords, vals, dims, **kw) -> AltoTensor:
     return AltoTensor.build(coords, vals, dims, **kw)
 
@@ -314,6 +326,17 @@ def selector_load(weights: np.ndarray | None):
         return
     w = np.ascontiguousarray(weights, dtype=np.float32)
     _check(lib().alto_selector_load(w.ctypes.data, w.size))
+
+
+DEFAULT_SELECTOR = os.path.join(_HERE, "selector_weights.f32")
+
+
+def load_default_selector() -> bool:
+    """Install the trained selector weights shipped with the package, if present."""
+    if not os.path.exists(DEFAULT_SELECTOR):
+        return False
+    selector_load(np.fromfile(DEFAULT_SELECTOR, dtype=np.float32))
+    return True
 
 
 def compute_units() -> int:

@@ -86,37 +86,15 @@ int make_layout(alto_tensor *t, int key_bits_req) {
     return ALTO_OK;
 }
 
-void free_partition(alto_tensor *t) {
-    Partition &p = t->part;
-    (void)hipFree(p.d_seg);
-    (void)hipFree(p.d_ivl);
-    for (int n = 0; n < kMaxModes; n++) {
-        (void)hipFree(p.d_cov[n]);
-        p.d_cov[n] = nullptr;
-    }
-    p.d_seg = nullptr;
-    p.d_ivl = nullptr;
-    p.L = 0;
-    p.h_seg.clear();
-    p.h_ivl.clear();
-    for (auto &kv : t->lists) (void)hipFree(kv.second.d);
-    t->lists.clear();
-    for (int n = 0; n < kMaxModes; n++) {
-        (void)hipFree(t->okeys[n]);
-        (void)hipFree(t->ovals[n]);
-        t->okeys[n] = nullptr;
-        t->ovals[n] = nullptr;
-    }
-}
-
 // Segment-local order by one mode: inside every line segment, a stable
 // reordering of the nonzeros by their mode coordinate (radix sort of
 // (segment, row) keys carrying the position), then a gather of index and
 // values into their own arrays.  Built once per mode and partition.
 int build_mode_order(alto_tensor *t, int mode, hipStream_t s) {
-    if (t->okeys[mode]) return ALTO_OK;
+    Partition &P = *t->part;
+    if (P.okeys[mode]) return ALTO_OK;
     const int64_t n = t->nnz;
-    const int L = t->part.L;
+    const int L = P.L;
     const int lbits = ceil_log2((uint64_t)std::max(1, L));
     const int bits = lbits + t->nbits[mode];
     const int wide = bits > 32;
@@ -145,7 +123,7 @@ int build_mode_order(alto_tensor *t, int mode, hipStream_t s) {
     ALTO_TRY2(hipMalloc(&ok2, (size_t)n * okb / 8));
     ALTO_TRY2(hipMalloc(&pos, (size_t)n * 4));
     ALTO_TRY2(hipMalloc(&pos2, (size_t)n * 4));
-    rc = launch_order_keys(t->key_bits, t->keys, t->part.d_seg, L, t->tab, mode, t->nbits[mode], wide, ok, pos, s);
+    rc = launch_order_keys(t->key_bits, t->keys, P.d_seg, L, t->tab, mode, t->nbits[mode], wide, ok, pos, s);
     if (!rc) rc = ensure_workspace(t, radix_sort_scratch(okb, n));
     bool in_alt = false;
     if (!rc)
@@ -155,9 +133,9 @@ int build_mode_order(alto_tensor *t, int mode, hipStream_t s) {
         return rc;
     }
     uint32_t *perm = in_alt ? pos2 : pos;
-    ALTO_TRY2(hipMalloc(&t->okeys[mode], kb * n));
-    ALTO_TRY2(hipMalloc(&t->ovals[mode], sizeof(float) * n));
-    rc = launch_gather(t->key_bits, t->keys, t->vals, perm, n, t->okeys[mode], t->ovals[mode], s);
+    ALTO_TRY2(hipMalloc(&P.okeys[mode], kb * n));
+    ALTO_TRY2(hipMalloc(&P.ovals[mode], sizeof(float) * n));
+    rc = launch_gather(t->key_bits, t->keys, t->vals, perm, n, P.okeys[mode], P.ovals[mode], s);
     cleanup();
 #undef ALTO_TRY2
     return rc;
@@ -172,12 +150,10 @@ int cu_count() {
 
 // Section 3.2: L equal-nonzero line segments, mode intervals, and the number
 // of segments whose interval holds each output row.
-int do_partition(alto_tensor *t, int L, hipStream_t s) {
-    if (L <= 0) L = 8 * cu_count();
-    free_partition(t);
-    Partition &p = t->part;
+int build_partition(alto_tensor *t, int Le, hipStream_t s, std::unique_ptr<Partition> *out) {
+    auto pp = std::make_unique<Partition>();
+    Partition &p = *pp;
     const int64_t M = t->nnz;
-    const int Le = M == 0 ? 0 : (int)std::min<int64_t>(L, M);
     p.L = Le;
     p.h_seg.resize(Le + 1);
     for (int l = 0; l <= Le; l++)
@@ -200,6 +176,37 @@ int do_partition(alto_tensor *t, int L, hipStream_t s) {
     if (Le > 0)
         ALTO_HIP(hipMemcpyAsync(p.h_ivl.data(), p.d_ivl, sizeof(uint32_t) * p.h_ivl.size(), hipMemcpyDeviceToHost, s));
     ALTO_HIP(hipStreamSynchronize(s));
+    *out = std::move(pp);
+    return ALTO_OK;
+}
+
+constexpr size_t kSparePartitions = 3;
+
+// Make the partition into L segments (L capped at nnz; 0 = 8 per compute
+// unit) the current one: reuse a recent one or build it.
+int select_partition(alto_tensor *t, int L, hipStream_t s) {
+    if (L <= 0) L = 8 * cu_count();
+    const int Le = t->nnz == 0 ? 0 : (int)std::min<int64_t>(L, t->nnz);
+    if (t->part && t->part->L == Le) return ALTO_OK;
+    for (size_t q = 0; q < t->spare.size(); q++)
+        if (t->spare[q]->L == Le) {
+            std::unique_ptr<Partition> p = std::move(t->spare[q]);
+            t->spare.erase(t->spare.begin() + q);
+            if (t->part) t->spare.push_back(std::move(t->part));
+            t->part = std::move(p);
+            return ALTO_OK;
+        }
+    std::unique_ptr<Partition> p;
+    const int rc = build_partition(t, Le, s, &p);
+    if (rc) return rc;
+    if (t->part) {
+        if (t->spare.size() >= kSparePartitions) {
+            ALTO_HIP(hipStreamSynchronize(s));  // work queued on the evicted partition has finished
+            t->spare.erase(t->spare.begin());
+        }
+        t->spare.push_back(std::move(t->part));
+    }
+    t->part = std::move(p);
     return ALTO_OK;
 }
 
@@ -223,19 +230,20 @@ int build_lists(alto_tensor *t, int mode, int strategy, int R, int prec, SegList
     const size_t budget = staged_lds_budget();
     const int cap_rows = strategy == ALTO_STRATEGY_STAGED ? (int)(budget / ((size_t)temp_stride(R) * 4)) : 0;
     const uint64_t key = ((uint64_t)mode << 40) | ((uint64_t)strategy << 32) | (uint64_t)(uint32_t)cap_rows;
-    auto it = t->lists.find(key);
-    if (it != t->lists.end()) {
+    Partition &P = *t->part;
+    auto it = P.lists.find(key);
+    if (it != P.lists.end()) {
         *out = &it->second;
         return ALTO_OK;
     }
-    const int L = t->part.L, N = t->N;
+    const int L = P.L, N = t->N;
     std::vector<int32_t> atomic_l;
     std::vector<int32_t> bucket[SegLists::kBuckets];
     // bucket bounds: 1/8, 1/2 and all of the row capacity
     const int bound[SegLists::kBuckets] = {std::max(1, cap_rows / 8), std::max(1, cap_rows / 2), cap_rows};
     for (int l = 0; l < L; l++) {
-        const uint32_t s0 = t->part.h_ivl[((size_t)l * N + mode) * 2 + 0];
-        const uint32_t e0 = t->part.h_ivl[((size_t)l * N + mode) * 2 + 1];
+        const uint32_t s0 = P.h_ivl[((size_t)l * N + mode) * 2 + 0];
+        const uint32_t e0 = P.h_ivl[((size_t)l * N + mode) * 2 + 1];
         const uint64_t w = (uint64_t)e0 - s0 + 1;
         if (cap_rows == 0 || w > (uint64_t)cap_rows) {
             atomic_l.push_back(l);
@@ -257,7 +265,7 @@ int build_lists(alto_tensor *t, int mode, int strategy, int R, int prec, SegList
     }
     ALTO_HIP(hipMalloc(&sl.d, sizeof(int32_t) * std::max<size_t>(1, all.size())));
     if (!all.empty()) ALTO_HIP(hipMemcpy(sl.d, all.data(), sizeof(int32_t) * all.size(), hipMemcpyHostToDevice));
-    auto ins = t->lists.emplace(key, sl);
+    auto ins = P.lists.emplace(key, sl);
     *out = &ins.first->second;
     return ALTO_OK;
 }
@@ -311,9 +319,8 @@ int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int p
     alto_exec plan;
     rc = resolve_strategy(t, mode, R, prec, ex, &plan);
     if (rc) return rc;
-    if (plan.num_segments > 0 && plan.num_segments != t->part.L && t->nnz > 0 &&
-        !(plan.num_segments > t->nnz && t->part.L == t->nnz)) {
-        rc = do_partition(t, plan.num_segments, s);
+    if (plan.num_segments > 0) {
+        rc = select_partition(t, plan.num_segments, s);
         if (rc) return rc;
     }
     const uint64_t outn = t->dims[mode] * (uint64_t)R;
@@ -332,7 +339,7 @@ int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int p
     const int nxcc = device_xcc_count();
     const size_t rep_bytes = (size_t)nxcc * outn * sizeof(float);
     const long force = env_long("ALTO_REPLICAS", -1);
-    bool use_rep = nxcc > 1 && rep_bytes <= ((size_t)2 << 30) && rep_bytes <= (size_t)t->nnz * 16;
+    bool use_rep = !sorted && nxcc > 1 && rep_bytes <= ((size_t)2 << 30) && rep_bytes <= (size_t)t->nnz * 16;
     if (force == 0) use_rep = false;
     if (force == 1) use_rep = nxcc > 1;
     if (use_rep && t->rep_bytes < rep_bytes) {
@@ -344,11 +351,11 @@ int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int p
     }
     if (use_rep) ALTO_HIP(hipMemsetAsync(t->rep, 0, rep_bytes, s));
     MtLaunch a{};
-    a.keys = sorted ? t->okeys[mode] : t->keys;
-    a.vals = sorted ? t->ovals[mode] : t->vals;
-    a.seg = t->part.d_seg;
-    a.ivl = t->part.d_ivl;
-    a.cov = t->part.d_cov[mode];
+    a.keys = sorted ? t->part->okeys[mode] : t->keys;
+    a.vals = sorted ? t->part->ovals[mode] : t->vals;
+    a.seg = t->part->d_seg;
+    a.ivl = t->part->d_ivl;
+    a.cov = t->part->d_cov[mode];
     for (int m = 0; m < t->N; m++) a.fac.p[m] = m == mode ? nullptr : factors[m];
     a.R = R;
     a.N = t->N;
@@ -368,7 +375,7 @@ int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int p
     };
     if (getenv("ALTO_DEBUG_PLAN"))
         fprintf(stderr, "[alto] mode %d R %d prec %d strategy %d L %d: atomic %d, staged %d/%d/%d (rows <= %d/%d/%d), replicas %d\n",
-                mode, R, prec, plan.strategy, t->part.L, sl->n_atomic, sl->n_bucket[0], sl->n_bucket[1],
+                mode, R, prec, plan.strategy, t->part->L, sl->n_atomic, sl->n_bucket[0], sl->n_bucket[1],
                 sl->n_bucket[2], sl->w_bucket[0], sl->w_bucket[1], sl->w_bucket[2], use_rep ? nxcc : 0);
     const int32_t *p = sl->d;
     const int32_t *bucket_p = p + sl->n_atomic;
@@ -491,9 +498,33 @@ int alto_build(const uint32_t *const *coords, const float *vals, int64_t nnz, co
         sums = nullptr;
     }
 #undef ALTO_TRY
-    rc = do_partition(t, o.num_segments, s);
+    rc = select_partition(t, o.num_segments, s);
     if (rc) return fail(rc);
     *out = t;
+    return ALTO_OK;
+}
+
+int alto_layout(const uint64_t *dims, int N, int key_bits, alto_info_t *out) {
+    g_err.clear();
+    if (!dims || !out) return set_error(ALTO_E_INVAL, "null argument");
+    if (N < 2 || N > kMaxModes) return set_error(ALTO_E_INVAL, "N must be in 2..8");
+    for (int n = 0; n < N; n++)
+        if (dims[n] == 0 || dims[n] > (1ull << 32)) return set_error(ALTO_E_INVAL, "dims must be in 1..2^32");
+    alto_tensor t;
+    t.N = N;
+    for (int n = 0; n < N; n++) t.dims[n] = dims[n];
+    const int rc = make_layout(&t, key_bits);
+    if (rc) return rc;
+    std::memset(out, 0, sizeof(*out));
+    out->N = N;
+    out->index_bits = t.B;
+    out->key_bits = t.key_bits;
+    for (int n = 0; n < N; n++) {
+        out->dims[n] = dims[n];
+        out->mode_bits[n] = t.nbits[n];
+        out->mask_lo[n] = t.mask_lo[n];
+        out->mask_hi[n] = t.mask_hi[n];
+    }
     return ALTO_OK;
 }
 
@@ -504,7 +535,7 @@ int alto_info(const alto_tensor *t, alto_info_t *out) {
     out->N = t->N;
     out->index_bits = t->B;
     out->key_bits = t->key_bits;
-    out->num_segments = t->part.L;
+    out->num_segments = t->part ? t->part->L : 0;
     out->nnz_in = t->nnz_in;
     out->nnz = t->nnz;
     for (int n = 0; n < t->N; n++) {
@@ -524,7 +555,7 @@ int alto_partition(alto_tensor *t, int num_segments, hipStream_t s) {
     g_err.clear();
     if (!t) return set_error(ALTO_E_INVAL, "null tensor handle");
     if (num_segments < 1) return set_error(ALTO_E_INVAL, "num_segments must be >= 1");
-    return do_partition(t, num_segments, s);
+    return select_partition(t, num_segments, s);
 }
 
 int alto_mttkrp(alto_tensor *t, const void *const *factors, int R, int prec, int mode, float *out,
@@ -546,11 +577,11 @@ int alto_export_keys(const alto_tensor *t, void *keys_out, float *vals_out, hipS
 int alto_export_partition(const alto_tensor *t, int64_t *seg_out, uint32_t *ivl_out, hipStream_t s) {
     g_err.clear();
     if (!t) return set_error(ALTO_E_INVAL, "null tensor handle");
-    const int L = t->part.L;
+    const int L = t->part->L;
     if (seg_out)
-        ALTO_HIP(hipMemcpyAsync(seg_out, t->part.d_seg, sizeof(int64_t) * (L + 1), hipMemcpyDeviceToDevice, s));
+        ALTO_HIP(hipMemcpyAsync(seg_out, t->part->d_seg, sizeof(int64_t) * (L + 1), hipMemcpyDeviceToDevice, s));
     if (ivl_out && L > 0)
-        ALTO_HIP(hipMemcpyAsync(ivl_out, t->part.d_ivl, sizeof(uint32_t) * L * t->N * 2, hipMemcpyDeviceToDevice, s));
+        ALTO_HIP(hipMemcpyAsync(ivl_out, t->part->d_ivl, sizeof(uint32_t) * L * t->N * 2, hipMemcpyDeviceToDevice, s));
     return ALTO_OK;
 }
 
@@ -558,7 +589,7 @@ int alto_export_coverage(const alto_tensor *t, int mode, uint32_t *cov_out, hipS
     g_err.clear();
     if (!t || !cov_out) return set_error(ALTO_E_INVAL, "null argument");
     if (mode < 0 || mode >= t->N) return set_error(ALTO_E_INVAL, "mode out of range");
-    ALTO_HIP(hipMemcpyAsync(cov_out, t->part.d_cov[mode], sizeof(uint32_t) * t->dims[mode], hipMemcpyDeviceToDevice, s));
+    ALTO_HIP(hipMemcpyAsync(cov_out, t->part->d_cov[mode], sizeof(uint32_t) * t->dims[mode], hipMemcpyDeviceToDevice, s));
     return ALTO_OK;
 }
 
@@ -576,7 +607,9 @@ int alto_round_bf16(const double *in, uint16_t *out, int64_t n, hipStream_t s) {
 
 void alto_free(alto_tensor *t) {
     if (!t) return;
-    free_partition(t);
+    (void)hipDeviceSynchronize();
+    t->part.reset();
+    t->spare.clear();
     (void)hipFree(t->rep);
     (void)hipFree(t->keys);
     (void)hipFree(t->vals);

@@ -297,13 +297,19 @@ __device__ __forceinline__ bool is_head(const K *keys, int64_t x) {
     return x == 0 || !KeyOps<K>::eq(keys[x], keys[x - 1]);
 }
 
+// Tiles of kScanTile positions; inside a tile, wave w owns positions
+// w*1024 .. w*1024+1023 and item j of a wave covers j*64 .. j*64+63, so every
+// load is a coalesced 64-wide read.
 template <typename K>
 __global__ __launch_bounds__(kThreads) void head_count_k(const K *__restrict__ keys, int64_t n, uint32_t *bcount) {
     __shared__ uint32_t lds[kWaves];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    const int lane = __lane_id(), wave = threadIdx.x / 64;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)wave * 64 * kScanItems;
     uint32_t c = 0;
-    for (int j = 0; j < kScanItems; j++)
-        if (base + j < n && is_head(keys, base + j)) c++;
+    for (int j = 0; j < kScanItems; j++) {
+        const int64_t x = base + (int64_t)j * 64 + lane;
+        if (x < n && is_head(keys, x)) c++;
+    }
     uint32_t tot;
     block_exclusive_scan(c, &tot, lds);
     if (threadIdx.x == 0) bcount[blockIdx.x] = tot;
@@ -313,22 +319,32 @@ template <typename K>
 __global__ __launch_bounds__(kThreads) void compact_k(const K *__restrict__ keys, const float *__restrict__ vals,
                                                       int64_t n, const uint64_t *__restrict__ boff,
                                                       K *__restrict__ kout, float *__restrict__ vout) {
-    __shared__ uint64_t lds[kWaves];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    uint64_t c = 0;
-    for (int j = 0; j < kScanItems; j++)
-        if (base + j < n && is_head(keys, base + j)) c++;
-    uint64_t tot;
-    uint64_t pos = block_exclusive_scan(c, &tot, lds) + boff[blockIdx.x];
+    __shared__ uint32_t wtot[kWaves];
+    const int lane = __lane_id(), wave = threadIdx.x / 64;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)wave * 64 * kScanItems;
+    const uint64_t lt = lanemask_lt();
+    uint32_t heads = 0;
     for (int j = 0; j < kScanItems; j++) {
-        const int64_t x = base + j;
-        if (x >= n || !is_head(keys, x)) continue;
-        const K key = keys[x];
-        float sum = vals[x];
-        for (int64_t y = x + 1; y < n && KeyOps<K>::eq(keys[y], key); y++) sum += vals[y];
-        kout[pos] = key;
-        vout[pos] = sum;
-        pos++;
+        const int64_t x = base + (int64_t)j * 64 + lane;
+        heads += (uint32_t)__builtin_popcountll(__ballot(x < n && is_head(keys, x)));
+    }
+    if (lane == 0) wtot[wave] = heads;
+    __syncthreads();
+    uint64_t pos = boff[blockIdx.x];
+    for (int w = 0; w < wave; w++) pos += wtot[w];
+    for (int j = 0; j < kScanItems; j++) {
+        const int64_t x = base + (int64_t)j * 64 + lane;
+        const bool h = x < n && is_head(keys, x);
+        const uint64_t m = __ballot(h);
+        if (h) {
+            const uint64_t p = pos + (uint64_t)__builtin_popcountll(m & lt);
+            const K key = keys[x];
+            float sum = vals[x];
+            for (int64_t y = x + 1; y < n && KeyOps<K>::eq(keys[y], key); y++) sum += vals[y];
+            kout[p] = key;
+            vout[p] = sum;
+        }
+        pos += (uint64_t)__builtin_popcountll(m);
     }
 }
 

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -96,16 +97,6 @@ struct CoordPtrs {
     const uint32_t *p[kMaxModes];
 };
 
-// ---------------------------------------------------------------- tensor
-struct Partition {
-    int L = 0;
-    int64_t *d_seg = nullptr;    // L+1
-    uint32_t *d_ivl = nullptr;   // L*N*2
-    uint32_t *d_cov[kMaxModes] = {};  // per mode, I_n
-    std::vector<int64_t> h_seg;
-    std::vector<uint32_t> h_ivl;
-};
-
 // Segment lists of one MTTKRP plan: segments run with atomics, and staged
 // segments bucketed by the LDS rows their mode interval needs.
 struct SegLists {
@@ -114,6 +105,38 @@ struct SegLists {
     int n_atomic = 0;
     int n_bucket[kBuckets] = {};
     int w_bucket[kBuckets] = {};
+};
+
+// ---------------------------------------------------------------- tensor
+// One cut of the ordered tensor into L equal-nonzero line segments, with
+// everything derived from it: mode intervals, per-row coverage, MTTKRP plans
+// and segment-local mode orders.  Owns its device memory.
+struct Partition {
+    int L = 0;
+    int64_t *d_seg = nullptr;         // L+1
+    uint32_t *d_ivl = nullptr;        // L*N*2
+    uint32_t *d_cov[kMaxModes] = {};  // per mode, I_n
+    std::vector<int64_t> h_seg;
+    std::vector<uint32_t> h_ivl;
+    // plans keyed by (mode, strategy, LDS row capacity)
+    std::map<uint64_t, SegLists> lists;
+    // segment-local mode orders: index and values reordered inside each
+    // segment by one mode's coordinate
+    void *okeys[kMaxModes] = {};
+    float *ovals[kMaxModes] = {};
+    Partition() = default;
+    Partition(const Partition &) = delete;
+    Partition &operator=(const Partition &) = delete;
+    ~Partition() {
+        (void)hipFree(d_seg);
+        (void)hipFree(d_ivl);
+        for (int n = 0; n < kMaxModes; n++) {
+            (void)hipFree(d_cov[n]);
+            (void)hipFree(okeys[n]);
+            (void)hipFree(ovals[n]);
+        }
+        for (auto &kv : lists) (void)hipFree(kv.second.d);
+    }
 };
 
 }  // namespace alto
@@ -131,19 +154,16 @@ struct alto_tensor {
     void *keys = nullptr;  // device, nnz * key_bits/8
     float *vals = nullptr; // device, nnz
     double norm2 = 0.0;
-    alto::Partition part;
+    // the current partition, and recently used ones (so that alternating
+    // segment counts between modes costs nothing after first use)
+    std::unique_ptr<alto::Partition> part;
+    std::vector<std::unique_ptr<alto::Partition>> spare;
     // reusable device workspace (grown on demand)
     void *ws = nullptr;
     size_t ws_bytes = 0;
-    // MTTKRP plans keyed by (mode, strategy, LDS row capacity); cleared on re-partition
-    std::map<uint64_t, alto::SegLists> lists;
     // per-XCD output replicas for atomic updates (grown on demand)
     float *rep = nullptr;
     size_t rep_bytes = 0;
-    // segment-local mode orderings (index and values reordered inside each
-    // line segment by one mode's coordinate); valid for the current partition
-    void *okeys[alto::kMaxModes] = {};
-    float *ovals[alto::kMaxModes] = {};
 };
 
 namespace alto {

@@ -14,7 +14,7 @@ namespace {
 
 constexpr int kT = 256;
 constexpr int kGramTile = 32;
-constexpr int kMaxParts = 1024;
+constexpr int kMaxParts = 256;
 
 __device__ __forceinline__ double load_factor(const void *A, int prec, uint64_t q) {
     if (prec == ALTO_PREC_BF16)
@@ -78,15 +78,22 @@ __global__ __launch_bounds__(kT) void sum_parts_k(const double *__restrict__ par
     out[e] = s;
 }
 
-// V = Hadamard of the Grams of every mode except `skip`; Cholesky with one
-// ridge retry; Vinv = L^-T L^-1.  One block.  status <- 1 on failure.
+// V = Hadamard of the Grams of every mode except `skip`; Cholesky V = L L^T
+// with one ridge retry; Vinv = L^-T L^-1 (column c solves L y = e_c, then
+// L^T x = y).  One block; the matrices live in LDS when R <= 64.
+// status <- 1 on failure.
 __global__ __launch_bounds__(kT) void normal_eq_k(const double *__restrict__ G, int N, int R, int skip,
-                                                  double *__restrict__ V, double *__restrict__ L,
+                                                  double *__restrict__ Vg, double *__restrict__ Lg,
                                                   double *__restrict__ Vinv, int *status) {
+    extern __shared__ double shm[];
     __shared__ int bad;
     __shared__ double ridge;
     if (*status) return;
     const int RR = R * R;
+    const bool in_lds = R <= 64;
+    double *V = in_lds ? shm : Vg;
+    double *L = in_lds ? shm + RR : Lg;
+    double *X = in_lds ? shm + 2 * RR : Vinv;
     for (int e = threadIdx.x; e < RR; e += kT) {
         double v = 1.0;
         for (int m = 0; m < N; m++)
@@ -101,15 +108,19 @@ __global__ __launch_bounds__(kT) void normal_eq_k(const double *__restrict__ G, 
             for (int r = 0; r < R; r++) tr += V[r * R + r];
             ridge = attempt == 0 ? 0.0 : 1e-10 * tr / R;
         }
-        __syncthreads();
         for (int e = threadIdx.x; e < RR; e += kT) L[e] = 0.0;
         __syncthreads();
         for (int j = 0; j < R; j++) {
-            if (threadIdx.x == 0) {
-                double d = V[j * R + j] + ridge;
-                for (int k = 0; k < j; k++) d -= L[j * R + k] * L[j * R + k];
-                if (!(d > 0.0)) bad = 1;
-                L[j * R + j] = d > 0.0 ? sqrt(d) : 1.0;
+            // diagonal: one wave reduces the dot product
+            if (threadIdx.x < 64) {
+                double d = 0.0;
+                for (int k = threadIdx.x; k < j; k += 64) d += L[j * R + k] * L[j * R + k];
+                for (int off = 32; off >= 1; off >>= 1) d += __shfl_xor(d, off);
+                if (threadIdx.x == 0) {
+                    d = V[j * R + j] + ridge - d;
+                    if (!(d > 0.0)) bad = 1;
+                    L[j * R + j] = d > 0.0 ? sqrt(d) : 1.0;
+                }
             }
             __syncthreads();
             const double djj = L[j * R + j];
@@ -127,73 +138,102 @@ __global__ __launch_bounds__(kT) void normal_eq_k(const double *__restrict__ G, 
         if (threadIdx.x == 0) *status = 1;
         return;
     }
-    // column c of Vinv: solve L y = e_c, then L^T x = y (x stored in Vinv[:, c])
     for (int c = threadIdx.x; c < R; c += kT) {
         for (int a = 0; a < R; a++) {
             double s = a == c ? 1.0 : 0.0;
-            for (int k = 0; k < a; k++) s -= L[a * R + k] * Vinv[k * R + c];
-            Vinv[a * R + c] = s / L[a * R + a];
+            for (int k = 0; k < a; k++) s -= L[a * R + k] * X[k * R + c];
+            X[a * R + c] = s / L[a * R + a];
         }
         for (int a = R - 1; a >= 0; a--) {
-            double s = Vinv[a * R + c];
-            for (int k = a + 1; k < R; k++) s -= L[k * R + a] * Vinv[k * R + c];
-            Vinv[a * R + c] = s / L[a * R + a];
+            double s = X[a * R + c];
+            for (int k = a + 1; k < R; k++) s -= L[k * R + a] * X[k * R + c];
+            X[a * R + c] = s / L[a * R + a];
         }
     }
+    if (in_lds) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < RR; e += kT) Vinv[e] = X[e];
+    }
 }
 
-// Atmp(i, c) = sum_k Mn(i, k) Vinv(k, c) in FP64; per-block column sums of squares.
-__global__ __launch_bounds__(kT) void solve_rows_k(const float *__restrict__ Mn, const double *__restrict__ Vinv,
-                                                   uint64_t I, int R, double *__restrict__ Atmp,
-                                                   double *__restrict__ colsq_part, const int *status) {
+// Row solves A(i, c) = sum_k Mn(i, k) Vinv(k, c) (FP64).  Thread (r, c) of a
+// block handles column c of rows r, r + rows_per_pass, ...; Vinv is staged in
+// LDS when R <= 64.  The solve is done twice (column norms first, then the
+// normalized store) rather than keeping an FP64 copy of A_n.
+
+__device__ __forceinline__ double solve_elem(const float *__restrict__ Mn, const double *__restrict__ vv, uint64_t i,
+                                             int R, int c) {
+    const float *m = Mn + i * R;
+    double s = 0.0;
+    for (int k = 0; k < R; k++) s += (double)m[k] * vv[k * R + c];
+    return s;
+}
+
+// Per-block column sums of squares of the solved rows (no store).
+__global__ __launch_bounds__(kT) void solve_norms_k(const float *__restrict__ Mn, const double *__restrict__ Vinv,
+                                                    uint64_t I, int R, double *__restrict__ colsq_part,
+                                                    const int *status) {
     extern __shared__ double sh[];
-    double *sv = sh;           // R*R when it fits, else unused
-    double *scol = sh + (R <= 64 ? R * R : 0);
     if (*status) return;
     const bool vin_lds = R <= 64;
+    double *sv = sh;
+    double *red = sh + (vin_lds ? R * R : 0);  // kT partial sums
     if (vin_lds)
         for (int e = threadIdx.x; e < R * R; e += kT) sv[e] = Vinv[e];
-    for (int e = threadIdx.x; e < R; e += kT) scol[e] = 0.0;
     __syncthreads();
     const double *vv = vin_lds ? sv : Vinv;
-    const uint64_t n = I * (uint64_t)R;
-    for (uint64_t e = (uint64_t)blockIdx.x * kT + threadIdx.x; e < n; e += (uint64_t)gridDim.x * kT) {
-        const uint64_t i = e / R;
-        const int c = (int)(e % R);
-        const float *m = Mn + i * R;
-        double s = 0.0;
-        for (int k = 0; k < R; k++) s += (double)m[k] * vv[k * R + c];
-        Atmp[e] = s;
-        atomicAdd(&scol[c], s * s);
+    const int rows = R >= kT ? 1 : kT / R;
+    const int r = threadIdx.x / R, c = threadIdx.x % R;
+    double acc = 0.0;
+    if (r < rows && threadIdx.x < rows * R) {
+        for (uint64_t i = (uint64_t)blockIdx.x * rows + r; i < I; i += (uint64_t)gridDim.x * rows) {
+            const double a = solve_elem(Mn, vv, i, R, c);
+            acc += a * a;
+        }
     }
+    red[threadIdx.x] = acc;
     __syncthreads();
-    for (int c = threadIdx.x; c < R; c += kT) colsq_part[(uint64_t)blockIdx.x * R + c] = scol[c];
+    // R <= kT, so every column has a thread in row 0 of the block
+    for (int cc = threadIdx.x; cc < R; cc += kT) {
+        double s = 0.0;
+        for (int q = 0; q < rows; q++) s += red[q * R + cc];
+        colsq_part[(uint64_t)blockIdx.x * R + cc] = s;
+    }
 }
 
+// lambda_c = sqrt(sum of the partial column sums of squares)
 __global__ __launch_bounds__(kT) void lambda_k(const double *__restrict__ colsq_part, int nparts, int R,
                                                double *__restrict__ lambda, const int *status) {
     if (*status) return;
-    for (int c = threadIdx.x; c < R; c += kT) {
+    for (int c = blockIdx.x * kT + threadIdx.x; c < R; c += gridDim.x * kT) {
         double s = 0.0;
         for (int p = 0; p < nparts; p++) s += colsq_part[(uint64_t)p * R + c];
         lambda[c] = sqrt(s);
     }
 }
 
-// A(i, c) = store(Atmp(i, c) / lambda_c) in the storage precision; for the
+// A(i, c) = store(solve(i, c) / lambda_c) in the storage precision; for the
 // last mode also the partial inner products sum_i lambda_c Mn(i,c) A(i,c).
-__global__ __launch_bounds__(kT) void normalize_k(const double *__restrict__ Atmp, const double *__restrict__ lambda,
-                                                  uint64_t I, int R, int prec, void *__restrict__ A,
-                                                  const float *__restrict__ Mn, double *__restrict__ inner_part,
+__global__ __launch_bounds__(kT) void normalize_k(const float *__restrict__ Mn, const double *__restrict__ Vinv,
+                                                  const double *__restrict__ lambda, uint64_t I, int R, int prec,
+                                                  void *__restrict__ A, double *__restrict__ inner_part,
                                                   const int *status) {
+    extern __shared__ double sh[];
     __shared__ double red[kT / 64];
     if (*status) return;
+    const bool vin_lds = R <= 64;
+    if (vin_lds)
+        for (int e = threadIdx.x; e < R * R; e += kT) sh[e] = Vinv[e];
+    __syncthreads();
+    const double *vv = vin_lds ? sh : Vinv;
     const uint64_t n = I * (uint64_t)R;
     double inner = 0.0;
     for (uint64_t e = (uint64_t)blockIdx.x * kT + threadIdx.x; e < n; e += (uint64_t)gridDim.x * kT) {
-        const int c = (int)(e % R);
+        const uint64_t i = e / R;
+        const int c = (int)(e - i * R);
         const double lam = lambda[c];
-        const double a = lam > 0.0 ? Atmp[e] / lam : Atmp[e];
+        const double s = solve_elem(Mn, vv, i, R, c);
+        const double a = lam > 0.0 ? s / lam : s;
         const float f = (float)a;
         double stored;
         if (prec == ALTO_PREC_BF16) {
@@ -261,13 +301,13 @@ __global__ __launch_bounds__(kT) void round_bf16_k(const double *__restrict__ in
 }
 
 int parts_for(uint64_t I) {
-    const uint64_t p = (I + 63) / 64;
+    const uint64_t p = (I + 255) / 256;
     return (int)std::max<uint64_t>(1, std::min<uint64_t>(kMaxParts, p));
 }
 
 struct AlsWs {
     float *Mn;
-    double *Atmp, *G, *V, *L, *Vinv, *parts, *colsq, *inner, *fit;
+    double *G, *V, *L, *Vinv, *parts, *colsq, *inner, *fit;
     int *status;
 };
 
@@ -308,7 +348,7 @@ int cp_als_impl(alto_tensor *t, int R, int iters, int prec, void *const *factors
     for (int n = 0; n < N; n++) maxI = std::max(maxI, t->dims[n]);
     const int RR = R * R;
     const int P = parts_for(maxI);
-    // the MTTKRP output and the FP64 solve buffer live in their own allocation
+    // the MTTKRP output and the FP64 work arrays live in their own allocation
     // (the tensor workspace may be regrown by a re-partition)
     size_t off = 0;
     auto take = [&](size_t b) {
@@ -316,16 +356,15 @@ int cp_als_impl(alto_tensor *t, int R, int iters, int prec, void *const *factors
         off += align256(b);
         return o;
     };
-    const size_t oMn = take(sizeof(float) * maxI * R), oAt = take(sizeof(double) * maxI * R),
+    const size_t oMn = take(sizeof(float) * maxI * R),
                  oG = take(sizeof(double) * N * RR), oV = take(sizeof(double) * RR), oL = take(sizeof(double) * RR),
                  oVi = take(sizeof(double) * RR), oP = take(sizeof(double) * (size_t)P * RR),
-                 oC = take(sizeof(double) * (size_t)kMaxParts * R), oI = take(sizeof(double) * kMaxParts),
+                 oC = take(sizeof(double) * (size_t)kMaxParts * R), oI = take(sizeof(double) * 2048),
                  oF = take(sizeof(double) * std::max(1, iters)), oS = take(sizeof(int));
     char *base = nullptr;
     ALTO_HIP(hipMalloc(&base, off));
     AlsWs w;
     w.Mn = (float *)(base + oMn);
-    w.Atmp = (double *)(base + oAt);
     w.G = (double *)(base + oG);
     w.V = (double *)(base + oV);
     w.L = (double *)(base + oL);
@@ -351,26 +390,29 @@ int cp_als_impl(alto_tensor *t, int R, int iters, int prec, void *const *factors
         rc = launch_gram(factors[n], prec, t->dims[n], R, w.G + (size_t)n * RR, w.parts, parts_for(t->dims[n]), s);
         if (rc) return done(rc);
     }
-    const size_t solve_lds = sizeof(double) * ((R <= 64 ? RR : 0) + R);
+    const size_t vin_lds = sizeof(double) * (R <= 64 ? RR : 0);
+    const size_t neq_lds = sizeof(double) * (R <= 64 ? 3 * RR : 0);
     for (int it = 0; it < iters; it++) {
         for (int n = 0; n < N; n++) {
             const uint64_t I = t->dims[n];
             rc = plan_and_run_mttkrp(t, (const void *const *)factors, R, prec, n, w.Mn, ex, s);
             if (rc) return done(rc);
-            normal_eq_k<<<1, kT, 0, s>>>(w.G, N, R, n, w.V, w.L, w.Vinv, w.status);
-            const uint64_t elems = I * (uint64_t)R;
-            const int gsolve = (int)std::min<uint64_t>(kMaxParts, (elems + kT - 1) / kT);
-            solve_rows_k<<<gsolve, kT, solve_lds, s>>>(w.Mn, w.Vinv, I, R, w.Atmp, w.colsq, w.status);
-            lambda_k<<<1, kT, 0, s>>>(w.colsq, gsolve, R, lambda, w.status);
+            normal_eq_k<<<1, kT, neq_lds, s>>>(w.G, N, R, n, w.V, w.L, w.Vinv, w.status);
+            const int rows = R >= kT ? 1 : kT / R;
+            const int gsolve = (int)std::max<uint64_t>(1, std::min<uint64_t>(kMaxParts, (I + rows - 1) / rows));
+            solve_norms_k<<<gsolve, kT, vin_lds + sizeof(double) * kT, s>>>(w.Mn, w.Vinv, I, R, w.colsq, w.status);
+            lambda_k<<<(R + kT - 1) / kT, kT, 0, s>>>(w.colsq, gsolve, R, lambda, w.status);
             const bool last = n == N - 1;
-            normalize_k<<<gsolve, kT, 0, s>>>(w.Atmp, lambda, I, R, prec, factors[n], w.Mn,
-                                               last ? w.inner : nullptr, w.status);
+            const uint64_t elems = I * (uint64_t)R;
+            const int gnorm = (int)std::min<uint64_t>(2048, (elems + kT - 1) / kT);
+            normalize_k<<<gnorm, kT, vin_lds, s>>>(w.Mn, w.Vinv, lambda, I, R, prec, factors[n],
+                                                   last ? w.inner : nullptr, w.status);
             const int Pn = parts_for(I);
             const int tiles = (R + kGramTile - 1) / kGramTile;
             gram_partial_k<<<dim3(Pn, tiles * tiles), kT, 0, s>>>(factors[n], prec, I, R, Pn, w.parts);
             sum_parts_k<<<(unsigned)((RR + kT - 1) / kT), kT, 0, s>>>(w.parts, Pn, RR, w.G + (size_t)n * RR,
                                                                      w.status);
-            if (last) fit_k<<<1, kT, 0, s>>>(w.G, N, R, lambda, w.inner, gsolve, t->norm2, w.fit + it, w.status);
+            if (last) fit_k<<<1, kT, 0, s>>>(w.G, N, R, lambda, w.inner, gnorm, t->norm2, w.fit + it, w.status);
             ALS_HIP(hipGetLastError());
         }
     }

@@ -64,3 +64,30 @@ def test_argument_errors_without_device_work():
     assert L.alto_mlp_adam(0, None, None, None, None, 0.1, 0.9, 0.99, 1e-8, 1, None) == alto.E_INVAL
     assert L.alto_round_bf16(None, None, -1, None) == alto.E_INVAL
     L.alto_free(None)
+
+
+@pytest.mark.skipif(not alto.lib_available(), reason="libalto.so not built")
+@pytest.mark.parametrize("dims", [(4, 8, 2), (1000, 800, 600), (2_000_000, 2_000_000, 20_000),
+                                  (1_000_000, 100_000, 10_000, 500), (10_000_000, 5_000_000, 2_000_000, 100_000, 1_000),
+                                  (1, 7, 1), (2 ** 32, 2 ** 32, 2 ** 20), (3, 3, 3, 3, 3, 3, 3, 3), (5, 5), (17, 16, 17)])
+def test_library_layout_matches_oracle(dims):
+    """The host half of alto_build (bit layout, Section 3.1) against the oracle."""
+    import oracle
+    got = alto.layout(dims)
+    ref = oracle.layout(dims)
+    assert got["index_bits"] == ref.B and got["mode_bits"] == ref.nbits and got["masks"] == ref.masks
+    assert got["key_bits"] == ref.W
+
+
+@pytest.mark.skipif(not alto.lib_available(), reason="libalto.so not built")
+def test_library_layout_errors():
+    with pytest.raises(alto.AltoError) as e:
+        alto.layout((2 ** 32,) * 5)
+    assert e.value.code == alto.E_TOO_WIDE
+    with pytest.raises(alto.AltoError) as e:
+        alto.layout((2 ** 20,) * 3, key_bits=32)
+    assert e.value.code == alto.E_TOO_WIDE
+    with pytest.raises(alto.AltoError) as e:
+        alto.layout((4, 0, 2))
+    assert e.value.code == alto.E_INVAL
+    assert alto.layout((1000, 800, 600), key_bits=128)["key_bits"] == 128

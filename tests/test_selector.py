@@ -1,0 +1,154 @@
+"""The learned execution selector: what the trained network gains over the
+method without it (the reuse rule of Section 3.3), judged against exhaustive
+timing on held-out tensors, and agreement between its implementations."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2102_10245_amd as alto
+from paper_2102_10245_amd import selector_train as st
+
+HERE = os.path.dirname(os.path.abspath(alto.__file__))
+
+
+def _weights():
+    w = np.fromfile(os.path.join(HERE, "selector_weights.f32"), dtype=np.float32)
+    F, H, K, nL = (int(x) for x in w[:4])
+    p = 4
+    mean, scale, fmin, fmax = (w[p + q * F:p + (q + 1) * F].astype(np.float64) for q in range(4))
+    p += 4 * F
+    Ls = w[p:p + nL]
+    p += nL
+    shapes = [(H, F), (H,), (H, H), (H,), (K, H), (K,)]
+    params = []
+    for sh in shapes:
+        n = int(np.prod(sh))
+        params.append(w[p:p + n].reshape(sh).astype(np.float64))
+        p += n
+    assert p == w.size
+    return dict(F=F, H=H, K=K, nL=nL, mean=mean, scale=scale, fmin=fmin, fmax=fmax, Ls=Ls, params=params, raw=w)
+
+
+def _corpus(split):
+    rows = st.load_corpus([os.path.join(HERE, "selector_corpus.jsonl")])
+    if split == "heldout":
+        return [r for r in rows if r["tensor"] >= st.N_TRAIN]
+    return [r for r in rows if r["tensor"] < st.N_TRAIN]
+
+
+def test_weights_layout_matches_candidates():
+    w = _weights()
+    assert (w["F"], w["H"], w["K"], w["nL"]) == (st.F, st.H, st.K, len(st.LS))
+    assert list(w["Ls"]) == list(st.LS)
+
+
+def test_network_beats_reuse_rule_on_heldout_tensors():
+    """Choices of the trained network (FP64 oracle forward) on the 100
+    held-out corpus tensors, timed exhaustively on MI355X when the corpus was
+    recorded: regret vs the best candidate, and speed-up over the paper's
+    reuse rule at the default segment count."""
+    w = _weights()
+    rows = _corpus("heldout")
+    X, T, _, M = st.arrays(rows)
+    net = oracle.MLP(*w["params"])
+    y, _ = net.forward((X - w["mean"]) / w["scale"])
+    y = np.where(M > 0, y, np.inf)
+    Tm = np.where(M > 0, T, np.inf)
+    choice = np.argmin(y, axis=1)
+    t_best = Tm.min(axis=1)
+    t_sel = Tm[np.arange(len(rows)), choice]
+    t_rule = np.array([Tm[q, st.heuristic_index(X[q, 2])] for q in range(len(rows))])
+    gain = np.exp(np.mean(np.log(t_rule / t_sel)))
+    regret = np.exp(np.mean(np.log(t_sel / t_best))) - 1
+    rule_regret = np.exp(np.mean(np.log(t_rule / t_best))) - 1
+    print(f"held-out: gain over reuse rule {gain:.3f}x, regret {regret:.3f} (reuse rule {rule_regret:.3f})")
+    assert len({r["tensor"] for r in rows}) == st.N_TOTAL - st.N_TRAIN
+    assert gain > 1.3
+    assert regret < 0.5 * rule_regret
+    assert t_sel.sum() < 0.7 * t_rule.sum()
+    # the recorded evaluation file says the same
+    ev = json.load(open(os.path.join(HERE, "selector_eval.json")))
+    assert ev["summary"]["heldout"]["gain_over_reuse_rule_geomean"] == pytest.approx(gain, rel=1e-3)
+
+
+def test_heldout_tensors_are_unseen():
+    fit = {r["tensor"] for r in _corpus("train")}
+    held = {r["tensor"] for r in _corpus("heldout")}
+    assert not fit & held
+
+
+def _gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+@pytest.mark.gpu
+@pytest.mark.skipif(not _gpu(), reason="needs a GPU")
+def test_hip_forward_matches_oracle_choice():
+    import torch
+    w = _weights()
+    rows = _corpus("heldout")
+    X, _, _, _ = st.arrays(rows)
+    xs = (X - w["mean"]) / w["scale"]
+    ref, _ = oracle.MLP(*w["params"]).forward(xs)
+    dev = torch.device("cuda", 0)
+    P = torch.from_numpy(w["raw"][4 + 4 * w["F"] + w["nL"]:].copy()).to(dev)
+    y, _ = alto.mlp_forward(P, torch.from_numpy(xs.astype(np.float32)).to(dev), w["F"], w["H"], w["K"])
+    y = y.cpu().numpy()
+    assert np.allclose(y, ref, rtol=1e-4, atol=1e-4)
+    # same decision wherever the oracle's best two are not within float noise
+    srt = np.sort(ref, axis=1)
+    clear = srt[:, 1] - srt[:, 0] > 1e-3
+    assert np.array_equal(np.argmin(y, axis=1)[clear], np.argmin(ref, axis=1)[clear])
+
+
+@pytest.mark.gpu
+@pytest.mark.skipif(not _gpu(), reason="needs a GPU")
+def test_library_selection_and_live_gain():
+    """alto_select (host inference inside libalto) agrees with the oracle
+    network on a built tensor, and its plan runs faster than the reuse rule's."""
+    import torch
+    import synth
+    rec = synth.scaled(synth.WORKLOADS["zipf4_1Mx100kx10kx500_150M"], 20_000_000)
+    coords, vals = synth.coo(rec)
+    c = torch.from_numpy(coords.view(np.int32)).cuda()
+    v = torch.from_numpy(vals).cuda()
+    t = alto.AltoTensor.build(c, v, rec.dims)
+    w = _weights()
+    net = oracle.MLP(*w["params"])
+    try:
+        assert alto.load_default_selector()
+        fs = [torch.from_numpy(f).cuda() for f in synth.factors(rec.seed + 1, rec.dims, rec.rank)]
+        sel_ms, rule_ms = 0.0, 0.0
+        for mode in range(4):
+            f = t.selector_features(mode, rec.rank, "f32").astype(np.float64)
+            y, _ = net.forward(((f - w["mean"]) / w["scale"])[None, :])
+            k = int(np.argmin(y[0]))
+            want = st.candidate(k)
+            assert t.select(mode, rec.rank, "f32") == want
+            out = torch.empty((rec.dims[mode], rec.rank), device="cuda")
+            for name, kw in (("sel", dict(strategy=want[0], num_segments=want[1])),
+                             ("rule", dict(strategy="staged" if f[2] > 2 else "atomic", num_segments=2048))):
+                t.mttkrp(fs, mode, out=out, **kw)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(5):
+                    t.mttkrp(fs, mode, out=out, **kw)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / 5
+                if name == "sel":
+                    sel_ms += ms
+                else:
+                    rule_ms += ms
+        print(f"selected plans {sel_ms:.2f} ms vs reuse rule {rule_ms:.2f} ms")
+        assert sel_ms < rule_ms
+    finally:
+        alto.selector_load(None)
+        t.close()
