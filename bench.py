@@ -171,7 +171,8 @@ def main():
     tot_ms = sum(m["ms"] for m in main_modes)
     achieved = tot_bytes / (tot_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(rec.name),
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
                 "kernel": "mttkrp_k (64-bit index, order 4, R=32, FP32 factors), mean over the 4 modes"}
 
     cpu = None
@@ -205,6 +206,22 @@ def main():
         "fit_f32": float(fit_f32[-1]) if len(fit_f32) else None,
     }
     print(json.dumps(out))
+
+
+def measured_traffic(workload):
+    """HBM bytes per MTTKRP launch from the committed counter profile, or None
+    when there is none for this workload or the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "mttkrp_zipf4_150M_r32_f32_hbm_traffic.json")
+    src = os.path.join(ROOT, "paper_2102_10245_amd", "csrc", "mttkrp_impl.h")
+    if not os.path.exists(path) or workload != "zipf4_1Mx100kx10kx500_150M":
+        return None
+    with open(path) as f:
+        prof = json.load(f)
+    with open(src, "rb") as f:
+        if hashlib.sha1(f.read()).hexdigest() != prof.get("kernel_source_sha1"):
+            return None
+    return round(prof["hbm_bytes_per_launch"])
 
 
 def log(msg):
