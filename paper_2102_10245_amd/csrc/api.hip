@@ -83,6 +83,29 @@ int make_layout(alto_tensor *t, int key_bits_req) {
         }
         t->tab.nruns[n] = nr;
     }
+    // compact form: coordinate bit k of mode n lands at bit coff[n] + k
+    int coff = 0;
+    for (int n = 0; n < N; n++) {
+        t->tab.coff[n] = (uint32_t)coff;
+        t->tab.cmask[n] = t->nbits[n] >= 32 ? 0xffffffffu : (1u << t->nbits[n]) - 1u;
+        coff += t->nbits[n];
+    }
+    t->h_ctab.clear();
+    if (t->key_bits <= 64) {
+        int cmap[64];
+        for (int p = 0; p < 64; p++) cmap[p] = -1;
+        for (int n = 0; n < N; n++)
+            for (int k = 0; k < t->nbits[n]; k++) cmap[where[n][k]] = (int)t->tab.coff[n] + k;
+        const int kb = t->key_bits / 8;
+        t->h_ctab.assign((size_t)byte_table_entries(t->key_bits) * kb, 0);
+        for (int j = 0; j < kb; j++)
+            for (int v = 0; v < 256; v++) {
+                uint64_t e = 0;
+                for (int b = 0; b < 8; b++)
+                    if (((v >> b) & 1) && cmap[8 * j + b] >= 0) e |= 1ull << cmap[8 * j + b];
+                std::memcpy(&t->h_ctab[((size_t)j * 256 + v) * kb], &e, kb);  // little-endian entry
+            }
+    }
     return ALTO_OK;
 }
 
@@ -218,7 +241,7 @@ long env_long(const char *name, long dflt) {
 // LDS budget of the Temp rows of a staged segment (one workgroup per CU at
 // the top of the range, several below it).
 size_t staged_lds_budget() {
-    static size_t budget = (size_t)std::min<long>(150 * 1024, std::max<long>(4096, env_long("ALTO_STAGE_LDS_BYTES", 96 * 1024)));
+    static size_t budget = (size_t)std::min<long>(140 * 1024, std::max<long>(4096, env_long("ALTO_STAGE_LDS_BYTES", 96 * 1024)));
     return budget;
 }
 
@@ -356,11 +379,21 @@ int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int p
     a.seg = t->part->d_seg;
     a.ivl = t->part->d_ivl;
     a.cov = t->part->d_cov[mode];
-    for (int m = 0; m < t->N; m++) a.fac.p[m] = m == mode ? nullptr : factors[m];
+    // the other modes first, in increasing order, then the output mode
+    for (int m = 0, j = 0; m <= t->N; m++) {
+        const int mm = m < t->N ? m : mode;
+        if (m < t->N && m == mode) continue;
+        if (m < t->N) a.fac.p[j] = factors[m];
+        a.dec.om[j] = mm;
+        a.dec.coff[j] = t->tab.coff[mm];
+        a.dec.cmask[j] = t->tab.cmask[mm];
+        j++;
+    }
     a.R = R;
     a.N = t->N;
     a.mode = mode;
     a.tab = t->tab;
+    a.ctab = t->ctab;
     a.out = out;
     a.rep = use_rep ? t->rep : nullptr;
     a.rep_stride = outn;
@@ -448,6 +481,10 @@ int alto_build(const uint32_t *const *coords, const float *vals, int64_t nnz, co
     } while (0)
     if (nnz > 0) {
         ALTO_TRY(hipMalloc(&t->keys, kb * nnz));
+        if (!t->h_ctab.empty()) {
+            ALTO_TRY(hipMalloc(&t->ctab, t->h_ctab.size()));
+            ALTO_TRY(hipMemcpyAsync(t->ctab, t->h_ctab.data(), t->h_ctab.size(), hipMemcpyHostToDevice, s));
+        }
         ALTO_TRY(hipMalloc(&t->vals, sizeof(float) * nnz));
         ALTO_TRY(hipMalloc(&keys_alt, kb * nnz));
         ALTO_TRY(hipMalloc(&vals_alt, sizeof(float) * nnz));
@@ -612,6 +649,7 @@ void alto_free(alto_tensor *t) {
     t->spare.clear();
     (void)hipFree(t->rep);
     (void)hipFree(t->keys);
+    (void)hipFree(t->ctab);
     (void)hipFree(t->vals);
     (void)hipFree(t->ws);
     delete t;

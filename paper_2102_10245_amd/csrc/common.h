@@ -75,6 +75,10 @@ struct RunTable {
     int N;
     int nruns[kMaxModes];
     uint32_t run[kMaxModes][kMaxRuns];
+    // Compact form (indices of at most 64 bits): mode n's coordinate is bits
+    // [coff[n], coff[n] + b_n) of the word that the byte tables assemble.
+    uint32_t coff[kMaxModes];
+    uint32_t cmask[kMaxModes];
 };
 
 __device__ __forceinline__ int run_kpos(uint32_t r) { return (int)(r & 0xffu); }
@@ -92,6 +96,22 @@ __device__ __forceinline__ uint32_t extract_mode(const K &key, const RunTable &t
     }
     return c;
 }
+
+// De-linearize all modes at once (indices of at most 64 bits).  Byte j of the
+// index, with value v, contributes table entry lt[j*256 + v]: the bits of v
+// moved to their places in the compact word, where the modes' coordinates sit
+// back to back.  The OR over the index bytes is a bit-level scatter of every
+// mode in one pass (Section 3.1's de-linearization).
+template <typename K>
+__device__ __forceinline__ K compact_index(const K key, const K *lt) {
+    K c = 0;
+#pragma unroll
+    for (int j = 0; j < (int)sizeof(K); j++) c |= lt[j * 256 + (int)((key >> (8 * j)) & 0xffu)];
+    return c;
+}
+
+// entries of the byte tables of a key width (0: the width has none)
+__host__ __device__ constexpr int byte_table_entries(int key_bits) { return key_bits <= 64 ? key_bits / 8 * 256 : 0; }
 
 struct CoordPtrs {
     const uint32_t *p[kMaxModes];
@@ -152,6 +172,8 @@ struct alto_tensor {
     alto::RunTable tab{};
     int64_t nnz_in = 0, nnz = 0;
     void *keys = nullptr;  // device, nnz * key_bits/8
+    void *ctab = nullptr;  // device byte tables of the compact form (key_bits <= 64)
+    std::vector<uint8_t> h_ctab;  // their host image (source of the upload)
     float *vals = nullptr; // device, nnz
     double norm2 = 0.0;
     // the current partition, and recently used ones (so that alternating

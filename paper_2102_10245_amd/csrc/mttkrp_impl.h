@@ -27,13 +27,51 @@
 // way, so the result does not depend on which XCD a workgroup runs on.
 #pragma once
 
+#include <type_traits>
+#include <utility>
+
 #include "common.h"
 
 namespace alto {
 
+// Factor matrices of the modes other than the output mode, in the order of
+// ModeDec (entry j is mode dec.om[j]).
 struct FactorPtrs {
     const void *p[kMaxModes];
 };
+
+// Per-launch decode plan: om[j] (j < N-1) are the other modes, om[N-1] the
+// output mode; coff/cmask locate each of them in the compact word.
+struct ModeDec {
+    int om[kMaxModes];
+    uint32_t coff[kMaxModes];
+    uint32_t cmask[kMaxModes];
+};
+
+template <int... Is, typename F>
+__device__ __forceinline__ void static_for_impl(std::integer_sequence<int, Is...>, F &&f) {
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+// f(integral_constant<int, i>) for i = 0 .. n-1, unrolled at compile time
+template <int n, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    static_for_impl(std::make_integer_sequence<int, n>{}, f);
+}
+
+// Value of lane k of this lane's group of G consecutive lanes.
+template <int G, int k>
+__device__ __forceinline__ uint32_t group_bcast(uint32_t x) {
+    if constexpr (G == 1) {
+        return x;
+    } else if constexpr (G == 64) {
+        return (uint32_t)__builtin_amdgcn_readlane((int)x, k);
+    } else {
+        static_assert(G <= 32 && (G & (G - 1)) == 0, "group size must be a power of two");
+        // ds_swizzle bit mode inside each 32-lane half: lane = (lane & and) | or
+        constexpr int pattern = ((32 - G) & 0x1f) | (k << 5);
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, pattern);
+    }
+}
 
 constexpr uint32_t kNoRow = 0xffffffffu;
 constexpr int kMaxReplicas = 16;
@@ -111,12 +149,14 @@ template <typename K, int NT, int RT, typename FT, bool kStaged>
 __global__ __launch_bounds__(1024) void mttkrp_k(
     const K *__restrict__ keys, const float *__restrict__ vals, const int64_t *__restrict__ seg,
     const uint32_t *__restrict__ ivl, const uint32_t *__restrict__ cov, FactorPtrs fac, int R_rt, int N_rt, int mode,
-    RunTable tab, float *__restrict__ out, float *__restrict__ rep, uint64_t rep_stride, int nrep,
-    const int32_t *__restrict__ seg_list, int n_list) {
+    RunTable tab, ModeDec dec, const K *__restrict__ ctab, int ctab_off, float *__restrict__ out, float *__restrict__ rep,
+    uint64_t rep_stride, int nrep, const int32_t *__restrict__ seg_list, int n_list) {
     using C = MtCfg<NT, RT, FT>;
     constexpr int VEC = C::kVec, G = C::kG, GPW = C::kGPW, NM = C::kNMax, NCOL = C::kCols, U = C::kU;
+    constexpr int NO = NM - 1;  // other modes
     constexpr bool QUEUE = C::kQueue && !kStaged;
     constexpr int QR = C::kQRows;
+    constexpr int kTab = byte_table_entries(8 * (int)sizeof(K));  // byte tables in LDS (keys <= 64 bits)
     const int N = NT ? NT : N_rt;
     const int R = RT ? RT : R_rt;
     extern __shared__ float smem[];
@@ -149,8 +189,15 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
         lo = ivl[((int64_t)l * N + mode) * 2 + 0];
         width = ivl[((int64_t)l * N + mode) * 2 + 1] - lo + 1;
         for (int q = threadIdx.x; q < (int)width * RP; q += blockDim.x) temp[q] = 0.f;
-        __syncthreads();
     }
+    K *const ltab = reinterpret_cast<K *>(smem + ctab_off);
+    if constexpr (kTab > 0) {
+        constexpr int n16 = kTab * (int)sizeof(K) / 16;
+        const uint4 *src = reinterpret_cast<const uint4 *>(ctab);
+        uint4 *dst = reinterpret_cast<uint4 *>(ltab);
+        for (int q = threadIdx.x; q < n16; q += blockDim.x) dst[q] = src[q];
+    }
+    if (kStaged || kTab > 0) __syncthreads();
 
     uint32_t cur = kNoRow;
     float acc[NCOL][VEC];
@@ -209,48 +256,55 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
             key_n = keys[pos];
             val_n = vals[pos];
         }
-        // de-linearize this lane's nonzero
-        uint32_t idx[NM];
+        // de-linearize this lane's nonzero: coordinates of the other modes
+        // (in the order of fac) and the output row
+        uint32_t idx[NO];
+        uint32_t myrow;
+        if constexpr (kTab > 0) {
+            const K cw = compact_index(key, ltab);  // key is 0 (all coordinates 0) past the end
 #pragma unroll
-        for (int m = 0; m < NM; m++) idx[m] = (m < N && ok) ? extract_mode(key, tab, m) : 0u;
-        uint32_t myrow = kNoRow;
+            for (int j = 0; j < NO; j++) idx[j] = j < N - 1 ? (uint32_t)(cw >> dec.coff[j]) & dec.cmask[j] : 0u;
+            myrow = (uint32_t)(cw >> dec.coff[N - 1]) & dec.cmask[N - 1];
+        } else {
 #pragma unroll
-        for (int m = 0; m < NM; m++)
-            if (m == mode && ok) myrow = idx[m];
+            for (int j = 0; j < NO; j++) idx[j] = (j < N - 1 && ok) ? extract_mode(key, tab, dec.om[j]) : 0u;
+            myrow = extract_mode(key, tab, mode);
+        }
+        if (!ok) myrow = kNoRow;
 
-        for (int k0 = 0; k0 < G; k0 += U) {
+        static_for<G / U>([&](auto kc) {
+            constexpr int k0 = decltype(kc)::value * U;
             uint32_t rows[U];
             float p[U][NCOL][VEC];
-#pragma unroll
-            for (int u = 0; u < U; u++) {
-                const int src = gw * G + k0 + u;
-                const uint32_t row = G == 1 ? myrow : (uint32_t)__shfl((int)myrow, src);
-                const float vv = G == 1 ? v : __shfl(v, src);
+            static_for<U>([&](auto uc) {
+                constexpr int u = decltype(uc)::value;
+                const uint32_t row = group_bcast<G, k0 + u>(myrow);
+                const float vv = __uint_as_float(group_bcast<G, k0 + u>(__float_as_uint(v)));
                 rows[u] = row;
 #pragma unroll
                 for (int a = 0; a < NCOL; a++)
 #pragma unroll
                     for (int e = 0; e < VEC; e++) p[u][a][e] = vv;
 #pragma unroll
-                for (int m = 0; m < NM; m++) {
-                    if (m >= N || m == mode) continue;
-                    const uint32_t im = G == 1 ? idx[m] : (uint32_t)__shfl((int)idx[m], src);
+                for (int j = 0; j < NO; j++) {
+                    if (j >= N - 1) continue;
+                    const uint32_t im = group_bcast<G, k0 + u>(idx[j]);
                     const uint64_t rowoff = (uint64_t)im * (uint64_t)R;
                     if constexpr (RT != 0) {
                         float f[VEC];
-                        FactorLoad<FT>::load(fac.p[m], rowoff + (uint64_t)c * VEC, f);
+                        FactorLoad<FT>::load(fac.p[j], rowoff + (uint64_t)c * VEC, f);
 #pragma unroll
                         for (int e = 0; e < VEC; e++) p[u][0][e] *= f[e];
                     } else {
 #pragma unroll
                         for (int a = 0; a < NCOL; a++) {
                             const int col = c + 64 * a;
-                            const float f = col < R ? FactorLoad<FT>::load1(fac.p[m], rowoff + col) : 0.f;
+                            const float f = col < R ? FactorLoad<FT>::load1(fac.p[j], rowoff + col) : 0.f;
                             p[u][a][0] *= f;
                         }
                     }
                 }
-            }
+            });
 #pragma unroll
             for (int u = 0; u < U; u++) {
                 const bool valid = rows[u] != kNoRow;
@@ -287,7 +341,7 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
             if constexpr (QUEUE) {
                 if (qn > QR - U * GPW) drain();
             }
-        }
+        });
     }
     if constexpr (QUEUE) {
         const uint64_t fl = __ballot(cur != kNoRow && c == 0);
@@ -327,6 +381,8 @@ struct MtLaunch {
     FactorPtrs fac;
     int R, N, mode;
     RunTable tab;
+    ModeDec dec;
+    const void *ctab;  // byte tables of the compact form (keys <= 64 bits)
     float *out;
     float *rep;        // replicas (nullptr: atomics straight to out)
     uint64_t rep_stride;
@@ -341,8 +397,12 @@ struct MtLaunch {
 template <typename K, int NT, int RT, typename FT>
 int launch_mt_cfg(const MtLaunch &a, hipStream_t s) {
     if (a.n_list <= 0) return ALTO_OK;
-    const size_t lds = a.staged ? (size_t)a.temp_rows * temp_stride(a.R) * 4
-                                : (size_t)mt_queue_bytes<NT, RT, FT>(a.threads);
+    const size_t main_lds = a.staged ? (size_t)a.temp_rows * temp_stride(a.R) * 4
+                                     : (size_t)mt_queue_bytes<NT, RT, FT>(a.threads);
+    const size_t tab_off = (main_lds + 15) / 16 * 16;
+    const size_t tab_bytes = (size_t)byte_table_entries(8 * (int)sizeof(K)) * sizeof(K);
+    const size_t lds = tab_off + tab_bytes;
+    if (tab_bytes && !a.ctab) return set_error(ALTO_E_INVAL, "internal: missing byte tables");
     const int per = (a.n_list + 7) / 8;
     const unsigned grid = (unsigned)per * 8;
     auto kern = a.staged ? mttkrp_k<K, NT, RT, FT, true> : mttkrp_k<K, NT, RT, FT, false>;
@@ -351,7 +411,8 @@ int launch_mt_cfg(const MtLaunch &a, hipStream_t s) {
         if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute(MaxDynamicSharedMemorySize)");
     }
     kern<<<grid, a.threads, lds, s>>>((const K *)a.keys, a.vals, a.seg, a.ivl, a.cov, a.fac, a.R, a.N, a.mode, a.tab,
-                                      a.out, a.rep, a.rep_stride, a.nrep, a.list, a.n_list);
+                                      a.dec, (const K *)a.ctab, (int)(tab_off / 4), a.out, a.rep, a.rep_stride, a.nrep,
+                                      a.list, a.n_list);
     ALTO_HIP(hipGetLastError());
     return ALTO_OK;
 }
