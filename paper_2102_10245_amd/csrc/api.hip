@@ -245,6 +245,13 @@ size_t staged_lds_budget() {
     return budget;
 }
 
+// workgroup size of launches that flush with atomics (ALTO_MT_THREADS:
+// 64..1024, a multiple of 64)
+int atomic_threads() {
+    const long v = env_long("ALTO_MT_THREADS", 256);
+    return (v >= 64 && v <= 1024 && v % 64 == 0) ? (int)v : 256;
+}
+
 // workgroup size for a staged launch whose Temp takes `bytes` of LDS
 int staged_threads(size_t bytes) { return bytes <= 40 * 1024 ? 256 : (bytes <= 80 * 1024 ? 512 : 1024); }
 
@@ -394,6 +401,9 @@ int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int p
     a.mode = mode;
     a.tab = t->tab;
     a.ctab = t->ctab;
+    a.wide = false;
+    for (int m = 0; m < t->N; m++)
+        if (m != mode && t->dims[m] * (uint64_t)R * (prec == ALTO_PREC_BF16 ? 2u : 4u) > 0xffffffffull) a.wide = true;
     a.out = out;
     a.rep = use_rep ? t->rep : nullptr;
     a.rep_stride = outn;
@@ -403,7 +413,7 @@ int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int p
         a.n_list = n;
         a.staged = staged;
         a.temp_rows = rows;
-        a.threads = staged ? staged_threads((size_t)rows * temp_stride(R) * 4) : 256;
+        a.threads = staged ? staged_threads((size_t)rows * temp_stride(R) * 4) : atomic_threads();
         return launch_mt(a, t->key_bits, prec, s);
     };
     if (getenv("ALTO_DEBUG_PLAN"))

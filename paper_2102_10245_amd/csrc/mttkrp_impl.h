@@ -79,18 +79,22 @@ constexpr int kMaxReplicas = 16;
 template <typename FT>
 struct FactorLoad;
 
+// Loads at a byte offset from a factor matrix: 32-bit offsets let the
+// gather use a scalar base plus one vector offset register.
 template <>
 struct FactorLoad<float> {
     static constexpr int kVec = 4;
-    __device__ __forceinline__ static void load(const void *base, uint64_t off, float (&x)[4]) {
-        const float4 q = *reinterpret_cast<const float4 *>(reinterpret_cast<const float *>(base) + off);
+    template <typename Off>
+    __device__ __forceinline__ static void load(const void *base, Off off, float (&x)[4]) {
+        const float4 q = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(base) + off);
         x[0] = q.x;
         x[1] = q.y;
         x[2] = q.z;
         x[3] = q.w;
     }
-    __device__ __forceinline__ static float load1(const void *base, uint64_t off) {
-        return reinterpret_cast<const float *>(base)[off];
+    template <typename Off>
+    __device__ __forceinline__ static float load1(const void *base, Off off) {
+        return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) + off);
     }
 };
 
@@ -99,8 +103,9 @@ __device__ __forceinline__ float bf16_to_f32(uint32_t b) { return __uint_as_floa
 template <>
 struct FactorLoad<uint16_t> {
     static constexpr int kVec = 8;
-    __device__ __forceinline__ static void load(const void *base, uint64_t off, float (&x)[8]) {
-        const uint4 q = *reinterpret_cast<const uint4 *>(reinterpret_cast<const uint16_t *>(base) + off);
+    template <typename Off>
+    __device__ __forceinline__ static void load(const void *base, Off off, float (&x)[8]) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(base) + off);
         x[0] = bf16_to_f32(q.x & 0xffffu);
         x[1] = bf16_to_f32(q.x >> 16);
         x[2] = bf16_to_f32(q.y & 0xffffu);
@@ -110,8 +115,9 @@ struct FactorLoad<uint16_t> {
         x[6] = bf16_to_f32(q.w & 0xffffu);
         x[7] = bf16_to_f32(q.w >> 16);
     }
-    __device__ __forceinline__ static float load1(const void *base, uint64_t off) {
-        return bf16_to_f32(reinterpret_cast<const uint16_t *>(base)[off]);
+    template <typename Off>
+    __device__ __forceinline__ static float load1(const void *base, Off off) {
+        return bf16_to_f32(*reinterpret_cast<const uint16_t *>(reinterpret_cast<const char *>(base) + off));
     }
 };
 
@@ -145,7 +151,7 @@ __device__ __forceinline__ uint32_t xcc_id() {
     return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 0xfu;
 }
 
-template <typename K, int NT, int RT, typename FT, bool kStaged>
+template <typename K, int NT, int RT, typename FT, bool kStaged, bool kWide>
 __global__ __launch_bounds__(1024) void mttkrp_k(
     const K *__restrict__ keys, const float *__restrict__ vals, const int64_t *__restrict__ seg,
     const uint32_t *__restrict__ ivl, const uint32_t *__restrict__ cov, FactorPtrs fac, int R_rt, int N_rt, int mode,
@@ -154,6 +160,7 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
     using C = MtCfg<NT, RT, FT>;
     constexpr int VEC = C::kVec, G = C::kG, GPW = C::kGPW, NM = C::kNMax, NCOL = C::kCols, U = C::kU;
     constexpr int NO = NM - 1;  // other modes
+    using Off = std::conditional_t<kWide, uint64_t, uint32_t>;  // factor byte offsets
     constexpr bool QUEUE = C::kQueue && !kStaged;
     constexpr int QR = C::kQRows;
     constexpr int kTab = byte_table_entries(8 * (int)sizeof(K));  // byte tables in LDS (keys <= 64 bits)
@@ -289,54 +296,60 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
                 for (int j = 0; j < NO; j++) {
                     if (j >= N - 1) continue;
                     const uint32_t im = group_bcast<G, k0 + u>(idx[j]);
-                    const uint64_t rowoff = (uint64_t)im * (uint64_t)R;
+                    const Off rowoff = (Off)im * (Off)(R * (int)sizeof(FT));
                     if constexpr (RT != 0) {
                         float f[VEC];
-                        FactorLoad<FT>::load(fac.p[j], rowoff + (uint64_t)c * VEC, f);
+                        FactorLoad<FT>::load(fac.p[j], rowoff + (Off)(c * VEC * (int)sizeof(FT)), f);
 #pragma unroll
                         for (int e = 0; e < VEC; e++) p[u][0][e] *= f[e];
                     } else {
 #pragma unroll
                         for (int a = 0; a < NCOL; a++) {
                             const int col = c + 64 * a;
-                            const float f = col < R ? FactorLoad<FT>::load1(fac.p[j], rowoff + col) : 0.f;
+                            const float f =
+                                col < R ? FactorLoad<FT>::load1(fac.p[j], rowoff + (Off)(col * (int)sizeof(FT))) : 0.f;
                             p[u][a][0] *= f;
                         }
                     }
                 }
             });
+            // Register run-combining.  A new row ends the current run, which is
+            // flushed; items past the end of the group's range carry row kNoRow,
+            // so they flush the last run and accumulate into a run that never is.
 #pragma unroll
             for (int u = 0; u < U; u++) {
-                const bool valid = rows[u] != kNoRow;
-                const bool brk = valid && rows[u] != cur && cur != kNoRow;
+                const bool nw = rows[u] != cur;
+                const bool fls = nw && cur != kNoRow;
                 if constexpr (QUEUE) {
                     // groups whose run ends append (row, accumulator) to the wave's queue
-                    const uint64_t fl = __ballot(brk && c == 0);
-                    if (brk) {
-                        const int slot = qn + __builtin_popcountll(fl & ((1ull << (gw * G)) - 1ull));
-                        float *e = qbuf + slot * (RT + 1);
+                    const uint64_t fl = __ballot(fls && c == 0);
+                    if (nw) {
+                        if (fls) {
+                            const int slot = qn + __builtin_popcountll(fl & ((1ull << (gw * G)) - 1ull));
+                            float *e = qbuf + slot * (RT + 1);
 #pragma unroll
-                        for (int q = 0; q < VEC; q++) e[c * VEC + q] = acc[0][q];
-                        if (c == 0) e[RT] = __uint_as_float(cur);
+                            for (int q = 0; q < VEC; q++) e[c * VEC + q] = acc[0][q];
+                            if (c == 0) e[RT] = __uint_as_float(cur);
+                        }
+                        cur = rows[u];
+#pragma unroll
+                        for (int e = 0; e < VEC; e++) acc[0][e] = 0.f;
                     }
                     qn += __builtin_popcountll(fl);
                 } else {
-                    if (brk) flush_direct(cur);
-                }
-                if (valid) {
-                    if (rows[u] != cur) {
+                    if (nw) {
+                        if (fls) flush_direct(cur);
                         cur = rows[u];
 #pragma unroll
                         for (int a = 0; a < NCOL; a++)
 #pragma unroll
-                            for (int e = 0; e < VEC; e++) acc[a][e] = p[u][a][e];
-                    } else {
-#pragma unroll
-                        for (int a = 0; a < NCOL; a++)
-#pragma unroll
-                            for (int e = 0; e < VEC; e++) acc[a][e] += p[u][a][e];
+                            for (int e = 0; e < VEC; e++) acc[a][e] = 0.f;
                     }
                 }
+#pragma unroll
+                for (int a = 0; a < NCOL; a++)
+#pragma unroll
+                    for (int e = 0; e < VEC; e++) acc[a][e] += p[u][a][e];
             }
             if constexpr (QUEUE) {
                 if (qn > QR - U * GPW) drain();
@@ -392,6 +405,7 @@ struct MtLaunch {
     int staged;
     int temp_rows;     // LDS Temp rows to reserve (staged launches)
     int threads;       // workgroup size (multiple of 64, <= 1024)
+    bool wide;         // some gathered factor matrix spans more than 4 GiB
 };
 
 template <typename K, int NT, int RT, typename FT>
@@ -405,7 +419,8 @@ int launch_mt_cfg(const MtLaunch &a, hipStream_t s) {
     if (tab_bytes && !a.ctab) return set_error(ALTO_E_INVAL, "internal: missing byte tables");
     const int per = (a.n_list + 7) / 8;
     const unsigned grid = (unsigned)per * 8;
-    auto kern = a.staged ? mttkrp_k<K, NT, RT, FT, true> : mttkrp_k<K, NT, RT, FT, false>;
+    auto kern = a.staged ? (a.wide ? mttkrp_k<K, NT, RT, FT, true, true> : mttkrp_k<K, NT, RT, FT, true, false>)
+                         : (a.wide ? mttkrp_k<K, NT, RT, FT, false, true> : mttkrp_k<K, NT, RT, FT, false, false>);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute(MaxDynamicSharedMemorySize)");
