@@ -1,7 +1,8 @@
 // CP-ALS on the GPU (Section 2.2 of the ALTO paper; standard alternating
 // least squares).  The MTTKRP of every mode runs on the ALTO tensor; the
-// R x R normal equations (Hadamard product of Grams, Cholesky factor,
-// inverse), the row solves, column norms, Grams and the fit are FP64.
+// R x R normal equations (Hadamard product of Grams, inverted with a
+// positive-pivot test and one ridge retry), the row solves, column norms,
+// Grams and the fit are FP64.
 // Factor storage is FP32 or BF16 (double -> binary32 -> bfloat16, both
 // round-to-nearest-even).
 #include <algorithm>
@@ -76,84 +77,6 @@ __global__ __launch_bounds__(kT) void sum_parts_k(const double *__restrict__ par
     double s = 0.0;
     for (int p = 0; p < nparts; p++) s += partials[(int64_t)p * n + e];
     out[e] = s;
-}
-
-// V = Hadamard of the Grams of every mode except `skip`; Cholesky V = L L^T
-// with one ridge retry; Vinv = L^-T L^-1 (column c solves L y = e_c, then
-// L^T x = y).  One block; the matrices live in LDS when R <= 64.
-// status <- 1 on failure.
-__global__ __launch_bounds__(kT) void normal_eq_k(const double *__restrict__ G, int N, int R, int skip,
-                                                  double *__restrict__ Vg, double *__restrict__ Lg,
-                                                  double *__restrict__ Vinv, int *status) {
-    extern __shared__ double shm[];
-    __shared__ int bad;
-    __shared__ double ridge;
-    if (*status) return;
-    const int RR = R * R;
-    const bool in_lds = R <= 64;
-    double *V = in_lds ? shm : Vg;
-    double *L = in_lds ? shm + RR : Lg;
-    double *X = in_lds ? shm + 2 * RR : Vinv;
-    for (int e = threadIdx.x; e < RR; e += kT) {
-        double v = 1.0;
-        for (int m = 0; m < N; m++)
-            if (m != skip) v *= G[(int64_t)m * RR + e];
-        V[e] = v;
-    }
-    __syncthreads();
-    for (int attempt = 0; attempt < 2; attempt++) {
-        if (threadIdx.x == 0) {
-            bad = 0;
-            double tr = 0.0;
-            for (int r = 0; r < R; r++) tr += V[r * R + r];
-            ridge = attempt == 0 ? 0.0 : 1e-10 * tr / R;
-        }
-        for (int e = threadIdx.x; e < RR; e += kT) L[e] = 0.0;
-        __syncthreads();
-        for (int j = 0; j < R; j++) {
-            // diagonal: one wave reduces the dot product
-            if (threadIdx.x < 64) {
-                double d = 0.0;
-                for (int k = threadIdx.x; k < j; k += 64) d += L[j * R + k] * L[j * R + k];
-                for (int off = 32; off >= 1; off >>= 1) d += __shfl_xor(d, off);
-                if (threadIdx.x == 0) {
-                    d = V[j * R + j] + ridge - d;
-                    if (!(d > 0.0)) bad = 1;
-                    L[j * R + j] = d > 0.0 ? sqrt(d) : 1.0;
-                }
-            }
-            __syncthreads();
-            const double djj = L[j * R + j];
-            for (int i = j + 1 + threadIdx.x; i < R; i += kT) {
-                double s = V[i * R + j];
-                for (int k = 0; k < j; k++) s -= L[i * R + k] * L[j * R + k];
-                L[i * R + j] = s / djj;
-            }
-            __syncthreads();
-        }
-        if (!bad) break;
-        __syncthreads();
-    }
-    if (bad) {
-        if (threadIdx.x == 0) *status = 1;
-        return;
-    }
-    for (int c = threadIdx.x; c < R; c += kT) {
-        for (int a = 0; a < R; a++) {
-            double s = a == c ? 1.0 : 0.0;
-            for (int k = 0; k < a; k++) s -= L[a * R + k] * X[k * R + c];
-            X[a * R + c] = s / L[a * R + a];
-        }
-        for (int a = R - 1; a >= 0; a--) {
-            double s = X[a * R + c];
-            for (int k = a + 1; k < R; k++) s -= L[k * R + a] * X[k * R + c];
-            X[a * R + c] = s / L[a * R + a];
-        }
-    }
-    if (in_lds) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < RR; e += kT) Vinv[e] = X[e];
-    }
 }
 
 // Row solves A(i, c) = sum_k Mn(i, k) Vinv(k, c) (FP64).  Thread (r, c) of a
@@ -294,6 +217,259 @@ __global__ __launch_bounds__(kT) void fit_k(const double *__restrict__ G, int N,
     }
 }
 
+// ---------------------------------------------------------------- rank-specialized update
+// For R in {8, 16, 32, 64} one mode update after the MTTKRP is: the normal
+// equations inverted in one block (Gauss-Jordan, below), a pass of row solves
+// for the column norms, and a pass that solves again, scales by lambda,
+// stores the factor and accumulates its Gram matrix (and, for the last mode,
+// the inner product of the fit) from the stored values.  Rows are processed
+// in tiles of 1024 / R rows staged in LDS; thread (row group, column c) keeps
+// column c of V^-1 in registers.
+
+// V = Hadamard of the Grams of every mode except `skip` (+ ridge on the
+// diagonal), inverted in place by Gauss-Jordan elimination without pivoting.
+// For a symmetric positive definite V every pivot is positive (the pivots are
+// the squared diagonal of its Cholesky factor), so a pivot <= 0 is the same
+// failure test as a failed Cholesky factorization; the ridge retry follows.
+// The matrix lives in LDS when R <= 128, else it is inverted in place in Vinv.
+__global__ __launch_bounds__(1024) void normal_eq_gj_k(const double *__restrict__ G, int N, int R, int skip,
+                                                       double *__restrict__ Vinv, int *status) {
+    extern __shared__ double shm[];
+    __shared__ double ridge;
+    if (*status) return;
+    const int RR = R * R;
+    const bool in_lds = R <= 128;
+    double *A = in_lds ? shm : Vinv;
+    double *colk = shm + (in_lds ? RR : 0);
+    double *rowk = colk + R;
+    const int nt = blockDim.x;
+    bool bad = false;
+    for (int attempt = 0; attempt < 2; attempt++) {
+        if (threadIdx.x == 0) {
+            double tr = 0.0;
+            for (int r = 0; r < R; r++) {
+                double v = 1.0;
+                for (int m = 0; m < N; m++)
+                    if (m != skip) v *= G[(int64_t)m * RR + r * R + r];
+                tr += v;
+            }
+            ridge = attempt == 0 ? 0.0 : 1e-10 * tr / R;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < RR; e += nt) {
+            double v = 1.0;
+            for (int m = 0; m < N; m++)
+                if (m != skip) v *= G[(int64_t)m * RR + e];
+            A[e] = v + ((e / R == e % R) ? ridge : 0.0);
+        }
+        __syncthreads();
+        bad = false;
+        for (int k = 0; k < R; k++) {
+            const double piv = A[k * R + k];
+            if (!(piv > 0.0)) {  // same value in every thread: a uniform exit
+                bad = true;
+                break;
+            }
+            for (int i = threadIdx.x; i < R; i += nt) {
+                colk[i] = A[i * R + k];
+                rowk[i] = A[k * R + i] / piv;
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < RR; e += nt) {
+                const int i = e / R, j = e - i * R;
+                double v;
+                if (i == k) v = j == k ? 1.0 / piv : rowk[j];
+                else if (j == k) v = -colk[i] / piv;
+                else v = A[e] - colk[i] * rowk[j];
+                A[e] = v;
+            }
+            __syncthreads();
+        }
+        if (!bad) break;
+        __syncthreads();
+    }
+    if (bad) {
+        if (threadIdx.x == 0) *status = 1;
+        return;
+    }
+    if (in_lds)
+        for (int e = threadIdx.x; e < RR; e += nt) Vinv[e] = A[e];
+}
+
+template <int R>
+struct SolveShape {
+    static constexpr int kRG = kT / R;       // row groups (threads per column)
+    static constexpr int kRPT = 4;           // rows per thread per tile
+    static constexpr int kTR = kRG * kRPT;   // rows per tile
+};
+
+// Stage rows [r0, r0 + TR) of Mn in LDS (zeros past I), one float4 per thread.
+template <int R>
+__device__ __forceinline__ void stage_rows(const float *__restrict__ Mn, uint64_t I, uint64_t r0, float *Ms) {
+    constexpr int TR = SolveShape<R>::kTR;
+    static_assert(TR * R == 4 * kT, "a tile is one float4 per thread");
+    const uint64_t e0 = r0 * R + 4u * threadIdx.x;
+    float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (r0 + (4u * threadIdx.x) / R < I) q = *reinterpret_cast<const float4 *>(Mn + e0);
+    reinterpret_cast<float4 *>(Ms)[threadIdx.x] = q;
+}
+
+template <int R>
+__device__ __forceinline__ double row_dot(const float *Ms, int r, const double (&vc)[R]) {
+    const float4 *m = reinterpret_cast<const float4 *>(Ms + r * R);
+    double s = 0.0;
+#pragma unroll
+    for (int k4 = 0; k4 < R / 4; k4++) {
+        const float4 q = m[k4];
+        s = fma((double)q.x, vc[4 * k4 + 0], s);
+        s = fma((double)q.y, vc[4 * k4 + 1], s);
+        s = fma((double)q.z, vc[4 * k4 + 2], s);
+        s = fma((double)q.w, vc[4 * k4 + 3], s);
+    }
+    return s;
+}
+
+// Pass 1: per-block column sums of squares of A = Mn V^-1.
+template <int R>
+__global__ __launch_bounds__(kT) void solve_colsq_k(const float *__restrict__ Mn, const double *__restrict__ Vinv,
+                                                    uint64_t I, double *__restrict__ colsq_part, const int *status) {
+    using S = SolveShape<R>;
+    __shared__ __align__(16) float Ms[S::kTR * R];
+    __shared__ double red[kT];
+    if (*status) return;
+    const int c = threadIdx.x % R, rg = threadIdx.x / R;
+    double vc[R];
+#pragma unroll
+    for (int k = 0; k < R; k++) vc[k] = Vinv[k * R + c];
+    double acc = 0.0;
+    const uint64_t ntiles = (I + S::kTR - 1) / S::kTR;
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        stage_rows<R>(Mn, I, tile * S::kTR, Ms);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < S::kRPT; q++) {
+            const double a = row_dot<R>(Ms, rg + S::kRG * q, vc);
+            acc = fma(a, a, acc);
+        }
+        __syncthreads();
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < R) {
+        double s = 0.0;
+        for (int g = 0; g < S::kRG; g++) s += red[g * R + threadIdx.x];
+        colsq_part[(uint64_t)blockIdx.x * R + threadIdx.x] = s;
+    }
+}
+
+// Pass 2: A(i, c) = store(solve(i, c) / lambda_c); per-block partial Gram of
+// the stored rows, and (inner_part != nullptr) the partial inner products
+// sum_i lambda_c Mn(i, c) A(i, c).
+template <int R>
+__global__ __launch_bounds__(kT) void normalize_gram_k(const float *__restrict__ Mn, const double *__restrict__ Vinv,
+                                                       const double *__restrict__ lambda, uint64_t I, int prec,
+                                                       void *__restrict__ A, double *__restrict__ gram_part,
+                                                       double *__restrict__ inner_part, const int *status) {
+    using S = SolveShape<R>;
+    constexpr int TR = S::kTR;
+    constexpr int EPT = (R * R + kT - 1) / kT;  // Gram entries per thread
+    __shared__ __align__(16) float Ms[TR * R];
+    __shared__ double As[TR * R];
+    __shared__ double red[kT / 64];
+    if (*status) return;
+    const int c = threadIdx.x % R, rg = threadIdx.x / R;
+    double vc[R];
+#pragma unroll
+    for (int k = 0; k < R; k++) vc[k] = Vinv[k * R + c];
+    const double lam = lambda[c];
+    double g[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; j++) g[j] = 0.0;
+    double inner = 0.0;
+    const uint64_t ntiles = (I + TR - 1) / TR;
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint64_t r0 = tile * TR;
+        stage_rows<R>(Mn, I, r0, Ms);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < S::kRPT; q++) {
+            const int r = rg + S::kRG * q;
+            const double s = row_dot<R>(Ms, r, vc);
+            const double a = lam > 0.0 ? s / lam : s;
+            const float f = (float)a;
+            double stored = 0.0;
+            if (r0 + r < I) {
+                const uint64_t e = (r0 + r) * R + c;
+                if (prec == ALTO_PREC_BF16) {
+                    const uint16_t b = f32_to_bf16_rne(f);
+                    reinterpret_cast<uint16_t *>(A)[e] = b;
+                    stored = (double)__uint_as_float((uint32_t)b << 16);
+                } else {
+                    reinterpret_cast<float *>(A)[e] = f;
+                    stored = (double)f;
+                }
+                inner += lam * (double)Ms[r * R + c] * stored;
+            }
+            As[r * R + c] = stored;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < EPT; j++) {
+            const int e = threadIdx.x + j * kT;
+            if (e < R * R) {
+                const int a = e / R, b = e - a * R;
+                double sum = g[j];
+                for (int r = 0; r < TR; r++) sum = fma(As[r * R + a], As[r * R + b], sum);
+                g[j] = sum;
+            }
+        }
+        __syncthreads();
+    }
+    double *P = gram_part + (uint64_t)blockIdx.x * R * R;
+#pragma unroll
+    for (int j = 0; j < EPT; j++) {
+        const int e = threadIdx.x + j * kT;
+        if (e < R * R) P[e] = g[j];
+    }
+    if (!inner_part) return;
+    for (int off = 32; off >= 1; off >>= 1) inner += __shfl_xor(inner, off);
+    if (__lane_id() == 0) red[threadIdx.x / 64] = inner;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int w = 0; w < kT / 64; w++) sum += red[w];
+        inner_part[blockIdx.x] = sum;
+    }
+}
+
+// Fixed-order reduction of partials in two levels: slice y of the grid sums
+// partials [y*P/S, (y+1)*P/S) into tmp[y], then sum_slices_k adds the S
+// slices.  out[e] = sum_p partials[p][e] for every launch size.
+constexpr int kSlices = 16;
+
+__global__ __launch_bounds__(kT) void sum_slices_partial_k(const double *__restrict__ partials, int nparts,
+                                                           int64_t n, double *__restrict__ tmp, const int *status) {
+    if (status && *status) return;
+    const int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (e >= n) return;
+    const int y = blockIdx.y;
+    const int p0 = (int)((int64_t)nparts * y / kSlices), p1 = (int)((int64_t)nparts * (y + 1) / kSlices);
+    double s = 0.0;
+    for (int p = p0; p < p1; p++) s += partials[(int64_t)p * n + e];
+    tmp[(int64_t)y * n + e] = s;
+}
+
+// out[e] = sum of the slices (sqrt_out: lambda = sqrt of the column sums)
+__global__ __launch_bounds__(kT) void sum_slices_k(const double *__restrict__ tmp, int64_t n,
+                                                   double *__restrict__ out, int sqrt_out, const int *status) {
+    if (status && *status) return;
+    const int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (e >= n) return;
+    double s = 0.0;
+    for (int y = 0; y < kSlices; y++) s += tmp[(int64_t)y * n + e];
+    out[e] = sqrt_out ? sqrt(s) : s;
+}
+
 __global__ __launch_bounds__(kT) void round_bf16_k(const double *__restrict__ in, uint16_t *__restrict__ out,
                                                    int64_t n) {
     for (int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x; e < n; e += (int64_t)gridDim.x * kT)
@@ -307,9 +483,31 @@ int parts_for(uint64_t I) {
 
 struct AlsWs {
     float *Mn;
-    double *G, *V, *L, *Vinv, *parts, *colsq, *inner, *fit;
+    double *G, *Vinv, *parts, *colsq, *inner, *fit, *tmp;
     int *status;
 };
+
+constexpr int kSolveBlocks = 512;  // blocks of the rank-specialized passes
+
+// One mode update after its MTTKRP (Mn), rank-specialized; see above.
+template <int R>
+int update_mode_r(AlsWs &w, uint64_t I, int prec, void *factor, double *lambda, bool last, int *nparts_inner,
+                  hipStream_t s) {
+    using S = SolveShape<R>;
+    const uint64_t ntiles = (I + S::kTR - 1) / S::kTR;
+    const int nb = (int)std::max<uint64_t>(1, std::min<uint64_t>(kSolveBlocks, ntiles));
+    solve_colsq_k<R><<<nb, kT, 0, s>>>(w.Mn, w.Vinv, I, w.colsq, w.status);
+    sum_slices_partial_k<<<dim3((R + kT - 1) / kT, kSlices), kT, 0, s>>>(w.colsq, nb, R, w.tmp, w.status);
+    sum_slices_k<<<(R + kT - 1) / kT, kT, 0, s>>>(w.tmp, R, lambda, 1, w.status);
+    normalize_gram_k<R><<<nb, kT, 0, s>>>(w.Mn, w.Vinv, lambda, I, prec, factor, w.parts,
+                                          last ? w.inner : nullptr, w.status);
+    const int64_t RR = (int64_t)R * R;
+    sum_slices_partial_k<<<dim3((unsigned)((RR + kT - 1) / kT), kSlices), kT, 0, s>>>(w.parts, nb, RR, w.tmp,
+                                                                                  w.status);
+    *nparts_inner = nb;
+    ALTO_HIP(hipGetLastError());
+    return ALTO_OK;
+}
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -357,21 +555,21 @@ int cp_als_impl(alto_tensor *t, int R, int iters, int prec, void *const *factors
         return o;
     };
     const size_t oMn = take(sizeof(float) * maxI * R),
-                 oG = take(sizeof(double) * N * RR), oV = take(sizeof(double) * RR), oL = take(sizeof(double) * RR),
-                 oVi = take(sizeof(double) * RR), oP = take(sizeof(double) * (size_t)P * RR),
-                 oC = take(sizeof(double) * (size_t)kMaxParts * R), oI = take(sizeof(double) * 2048),
+                 oG = take(sizeof(double) * N * RR),
+                 oVi = take(sizeof(double) * RR), oP = take(sizeof(double) * (size_t)std::max(P, kSolveBlocks) * RR),
+                 oC = take(sizeof(double) * (size_t)std::max(kMaxParts, kSolveBlocks) * R),
+                 oT = take(sizeof(double) * (size_t)kSlices * RR), oI = take(sizeof(double) * 2048),
                  oF = take(sizeof(double) * std::max(1, iters)), oS = take(sizeof(int));
     char *base = nullptr;
     ALTO_HIP(hipMalloc(&base, off));
     AlsWs w;
     w.Mn = (float *)(base + oMn);
     w.G = (double *)(base + oG);
-    w.V = (double *)(base + oV);
-    w.L = (double *)(base + oL);
     w.Vinv = (double *)(base + oVi);
     w.parts = (double *)(base + oP);
     w.colsq = (double *)(base + oC);
     w.inner = (double *)(base + oI);
+    w.tmp = (double *)(base + oT);
     w.fit = (double *)(base + oF);
     w.status = (int *)(base + oS);
     int rc = ALTO_OK;
@@ -391,18 +589,38 @@ int cp_als_impl(alto_tensor *t, int R, int iters, int prec, void *const *factors
         if (rc) return done(rc);
     }
     const size_t vin_lds = sizeof(double) * (R <= 64 ? RR : 0);
-    const size_t neq_lds = sizeof(double) * (R <= 64 ? 3 * RR : 0);
+    const size_t neq_lds = sizeof(double) * ((R <= 128 ? RR : 0) + 2 * R);
+    const int neq_threads = RR <= 1024 ? 256 : 1024;
+    if (neq_lds > 64 * 1024)
+        ALS_HIP(hipFuncSetAttribute((const void *)normal_eq_gj_k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)neq_lds));
+    const bool special = R == 8 || R == 16 || R == 32 || R == 64;
     for (int it = 0; it < iters; it++) {
         for (int n = 0; n < N; n++) {
             const uint64_t I = t->dims[n];
             rc = plan_and_run_mttkrp(t, (const void *const *)factors, R, prec, n, w.Mn, ex, s);
             if (rc) return done(rc);
-            normal_eq_k<<<1, kT, neq_lds, s>>>(w.G, N, R, n, w.V, w.L, w.Vinv, w.status);
+            normal_eq_gj_k<<<1, neq_threads, neq_lds, s>>>(w.G, N, R, n, w.Vinv, w.status);
+            const bool last = n == N - 1;
+            if (special) {
+                int nin = 0;
+                switch (R) {
+                    case 8: rc = update_mode_r<8>(w, I, prec, factors[n], lambda, last, &nin, s); break;
+                    case 16: rc = update_mode_r<16>(w, I, prec, factors[n], lambda, last, &nin, s); break;
+                    case 32: rc = update_mode_r<32>(w, I, prec, factors[n], lambda, last, &nin, s); break;
+                    default: rc = update_mode_r<64>(w, I, prec, factors[n], lambda, last, &nin, s); break;
+                }
+                if (rc) return done(rc);
+                sum_slices_k<<<(unsigned)((RR + kT - 1) / kT), kT, 0, s>>>(w.tmp, RR, w.G + (size_t)n * RR, 0,
+                                                                           w.status);
+                if (last) fit_k<<<1, kT, 0, s>>>(w.G, N, R, lambda, w.inner, nin, t->norm2, w.fit + it, w.status);
+                ALS_HIP(hipGetLastError());
+                continue;
+            }
             const int rows = R >= kT ? 1 : kT / R;
             const int gsolve = (int)std::max<uint64_t>(1, std::min<uint64_t>(kMaxParts, (I + rows - 1) / rows));
             solve_norms_k<<<gsolve, kT, vin_lds + sizeof(double) * kT, s>>>(w.Mn, w.Vinv, I, R, w.colsq, w.status);
             lambda_k<<<(R + kT - 1) / kT, kT, 0, s>>>(w.colsq, gsolve, R, lambda, w.status);
-            const bool last = n == N - 1;
             const uint64_t elems = I * (uint64_t)R;
             const int gnorm = (int)std::min<uint64_t>(2048, (elems + kT - 1) / kT);
             normalize_k<<<gnorm, kT, vin_lds, s>>>(w.Mn, w.Vinv, lambda, I, R, prec, factors[n],

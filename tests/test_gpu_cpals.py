@@ -6,7 +6,7 @@ import pytest
 import oracle
 import paper_2102_10245_amd as alto
 import synth
-from gpu_common import factors_dev, gpu_ok, to_dev
+from gpu_common import factors_dev, gpu_ok, rel_fro, to_dev
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_ok(), reason="needs a GPU")]
 
@@ -76,4 +76,39 @@ def test_cp_als_zero_iterations_and_errors():
     fd = factors_dev(synth.factors(3, rec.dims, 4))
     lam, fit = t.cp_als(fd, 0)
     assert fit.shape == (0,)
+    t.close()
+
+
+@pytest.mark.parametrize("R", [5, 8, 32, 64, 96, 160])
+def test_cp_als_ranks_match_oracle(R):
+    # ranks with a specialized update (8, 32, 64) and the generic one, with
+    # the normal equations in LDS (R <= 128) and in device memory (160)
+    rec = synth.scaled(synth.WORKLOADS["uniform3_1000x800x600_100k"], 30_000)
+    coords, vals = synth.coo(rec)
+    c, v = to_dev(coords, vals)
+    t = alto.AltoTensor.build(c, v, rec.dims)
+    init = synth.factors(rec.seed + 7, rec.dims, R)
+    oA, olam, ofit = oracle.cp_als(rec.dims, coords, vals, init, 3)
+    fd = factors_dev(init)
+    lam, fit = t.cp_als(fd, 3)
+    print("R", R, "fit", fit, "oracle", ofit, flush=True)
+    assert np.all(np.abs(fit - ofit) <= 1e-5)
+    assert np.allclose(lam.cpu().numpy(), olam, rtol=1e-3)
+    for f, a in zip(fd, oA):
+        assert rel_fro(f.cpu().numpy(), a) <= 1e-3
+    t.close()
+
+
+def test_cp_als_singular_normal_equations():
+    # all-zero factors: every Gram is zero, so is the ridge, and the normal
+    # equations stay singular -> ALTO_E_NOTSPD
+    rec = synth.Recipe("z", (30, 20, 10), 500, (), seed=4)
+    coords, vals = synth.coo(rec)
+    c, v = to_dev(coords, vals)
+    t = alto.AltoTensor.build(c, v, rec.dims)
+    for R in (4, 32):
+        fd = factors_dev([np.zeros((d, R), np.float32) for d in rec.dims])
+        with pytest.raises(alto.AltoError) as e:
+            t.cp_als(fd, 2)
+        assert e.value.code == alto.E_NOTSPD
     t.close()
