@@ -402,8 +402,30 @@ int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int p
     a.tab = t->tab;
     a.ctab = t->ctab;
     a.wide = false;
+    const uint64_t fs = prec == ALTO_PREC_BF16 ? 2u : 4u;
     for (int m = 0; m < t->N; m++)
-        if (m != mode && t->dims[m] * (uint64_t)R * (prec == ALTO_PREC_BF16 ? 2u : 4u) > 0xffffffffull) a.wide = true;
+        if (m != mode && t->dims[m] * (uint64_t)R * fs > 0xffffffffull) a.wide = true;
+    // Factor matrices of other modes small enough to sit in LDS (smallest
+    // first, ALTO_STAGE_FACTOR_BYTES in total) are gathered from there; such
+    // launches use 1024-thread workgroups so one copy serves 16 waves, which
+    // needs segments long enough to keep 128 lane groups in long runs.
+    a.dec.smask = 0;
+    const int64_t seg_len = t->nnz / std::max(1, t->part->L);
+    if ((R == 8 || R == 16 || R == 32 || R == 64) && seg_len >= 8192) {
+        const uint64_t budget = (uint64_t)std::max<long>(0, env_long("ALTO_STAGE_FACTOR_BYTES", 64 * 1024));
+        int js[kMaxModes];
+        for (int j = 0; j < t->N - 1; j++) js[j] = j;
+        std::sort(js, js + t->N - 1, [&](int x, int y) { return t->dims[a.dec.om[x]] < t->dims[a.dec.om[y]]; });
+        uint64_t used = 0;
+        for (int q = 0; q < t->N - 1; q++) {
+            const int j = js[q];
+            const uint64_t bytes = t->dims[a.dec.om[j]] * (uint64_t)R * fs;
+            if (used + bytes > budget) break;
+            a.dec.smask |= 1u << j;
+            a.dec.sbytes[j] = (uint32_t)bytes;
+            used += bytes;
+        }
+    }
     a.out = out;
     a.rep = use_rep ? t->rep : nullptr;
     a.rep_stride = outn;
@@ -413,7 +435,8 @@ int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int p
         a.n_list = n;
         a.staged = staged;
         a.temp_rows = rows;
-        a.threads = staged ? staged_threads((size_t)rows * temp_stride(R) * 4) : atomic_threads();
+        a.threads = staged ? staged_threads((size_t)rows * temp_stride(R) * 4)
+                           : (a.dec.smask ? 1024 : atomic_threads());
         return launch_mt(a, t->key_bits, prec, s);
     };
     if (getenv("ALTO_DEBUG_PLAN"))

@@ -41,11 +41,16 @@ struct FactorPtrs {
 };
 
 // Per-launch decode plan: om[j] (j < N-1) are the other modes, om[N-1] the
-// output mode; coff/cmask locate each of them in the compact word.
+// output mode; coff/cmask locate each of them in the compact word.  Other
+// modes with bit j of smask have their whole factor matrix (sbytes[j] bytes)
+// copied to LDS at byte offset soff[j] and are gathered from there.
 struct ModeDec {
     int om[kMaxModes];
     uint32_t coff[kMaxModes];
     uint32_t cmask[kMaxModes];
+    uint32_t smask;
+    uint32_t soff[kMaxModes];
+    uint32_t sbytes[kMaxModes];
 };
 
 template <int... Is, typename F>
@@ -133,7 +138,7 @@ struct MtCfg {
     static constexpr int kU = kG >= 4 ? 4 : kG;               // nonzeros in flight per group
     // flush queue (rank-specialized atomic path): rows per wave
     static constexpr bool kQueue = RT != 0 && RT <= 64;
-    static constexpr int kQRows = kQueue ? 4 * kGPW : 0;      // a tile of U items flushes at most U rows per group
+    static constexpr int kQRows = kQueue ? 2 * kGPW : 0;      // drained once it holds more than one row per group
 };
 
 // LDS row stride of Temp: one float of padding spreads rows over the banks.
@@ -204,7 +209,16 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
         uint4 *dst = reinterpret_cast<uint4 *>(ltab);
         for (int q = threadIdx.x; q < n16; q += blockDim.x) dst[q] = src[q];
     }
-    if (kStaged || kTab > 0) __syncthreads();
+    if constexpr (RT != 0 && !kStaged) {
+        // small factor matrices of other modes, staged whole
+        for (int j = 0; j < N - 1; j++) {
+            if (!((dec.smask >> j) & 1u)) continue;
+            const uint4 *src = reinterpret_cast<const uint4 *>(fac.p[j]);
+            uint4 *dst = reinterpret_cast<uint4 *>(reinterpret_cast<char *>(smem) + dec.soff[j]);
+            for (uint32_t q = threadIdx.x; q < dec.sbytes[j] / 16u; q += blockDim.x) dst[q] = src[q];
+        }
+    }
+    if (kStaged || kTab > 0 || dec.smask) __syncthreads();
 
     uint32_t cur = kNoRow;
     float acc[NCOL][VEC];
@@ -299,7 +313,13 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
                     const Off rowoff = (Off)im * (Off)(R * (int)sizeof(FT));
                     if constexpr (RT != 0) {
                         float f[VEC];
-                        FactorLoad<FT>::load(fac.p[j], rowoff + (Off)(c * VEC * (int)sizeof(FT)), f);
+                        if (!kStaged && ((dec.smask >> j) & 1u)) {
+                            const uint32_t lo = dec.soff[j] + im * (uint32_t)(R * (int)sizeof(FT)) +
+                                                (uint32_t)(c * VEC * (int)sizeof(FT));
+                            FactorLoad<FT>::load(reinterpret_cast<const char *>(smem), lo, f);
+                        } else {
+                            FactorLoad<FT>::load(fac.p[j], rowoff + (Off)(c * VEC * (int)sizeof(FT)), f);
+                        }
 #pragma unroll
                         for (int e = 0; e < VEC; e++) p[u][0][e] *= f[e];
                     } else {
@@ -336,6 +356,7 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
                         for (int e = 0; e < VEC; e++) acc[0][e] = 0.f;
                     }
                     qn += __builtin_popcountll(fl);
+                    if (qn > GPW) drain();  // room for the next item's flushes
                 } else {
                     if (nw) {
                         if (fls) flush_direct(cur);
@@ -350,9 +371,6 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
                 for (int a = 0; a < NCOL; a++)
 #pragma unroll
                     for (int e = 0; e < VEC; e++) acc[a][e] += p[u][a][e];
-            }
-            if constexpr (QUEUE) {
-                if (qn > QR - U * GPW) drain();
             }
         });
     }
@@ -415,7 +433,16 @@ int launch_mt_cfg(const MtLaunch &a, hipStream_t s) {
                                      : (size_t)mt_queue_bytes<NT, RT, FT>(a.threads);
     const size_t tab_off = (main_lds + 15) / 16 * 16;
     const size_t tab_bytes = (size_t)byte_table_entries(8 * (int)sizeof(K)) * sizeof(K);
-    const size_t lds = tab_off + tab_bytes;
+    size_t lds = tab_off + tab_bytes;
+    ModeDec dec = a.dec;
+    if (RT == 0 || a.staged) dec.smask = 0;
+    for (int j = 0; j < a.N - 1; j++)
+        if ((dec.smask >> j) & 1u) {
+            lds = (lds + 15) / 16 * 16;
+            dec.soff[j] = (uint32_t)lds;
+            lds += dec.sbytes[j];
+        }
+    if (lds > 160 * 1024) return set_error(ALTO_E_INVAL, "internal: MTTKRP launch exceeds the LDS size");
     if (tab_bytes && !a.ctab) return set_error(ALTO_E_INVAL, "internal: missing byte tables");
     const int per = (a.n_list + 7) / 8;
     const unsigned grid = (unsigned)per * 8;
@@ -426,7 +453,7 @@ int launch_mt_cfg(const MtLaunch &a, hipStream_t s) {
         if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute(MaxDynamicSharedMemorySize)");
     }
     kern<<<grid, a.threads, lds, s>>>((const K *)a.keys, a.vals, a.seg, a.ivl, a.cov, a.fac, a.R, a.N, a.mode, a.tab,
-                                      a.dec, (const K *)a.ctab, (int)(tab_off / 4), a.out, a.rep, a.rep_stride, a.nrep,
+                                      dec, (const K *)a.ctab, (int)(tab_off / 4), a.out, a.rep, a.rep_stride, a.nrep,
                                       a.list, a.n_list);
     ALTO_HIP(hipGetLastError());
     return ALTO_OK;
