@@ -134,13 +134,19 @@ def load_corpus(paths):
     return rows
 
 
+# Regression targets are clipped at a 2x slowdown: the choice is the argmin,
+# so only the ordering of the candidates near the fastest one matters, and
+# unclipped targets let the slowest candidates dominate the squared error.
+TARGET_CLIP = 1.0
+
+
 def arrays(rows):
     X = np.array([r["features"] for r in rows], np.float64)
     T = np.array([r["ms"] for r in rows], np.float64)
     mask = np.isfinite(T) & (T > 0)
     logt = np.where(mask, np.log2(np.where(mask, T, 1.0)), 0.0)
     best = np.min(np.where(mask, logt, np.inf), axis=1, keepdims=True)
-    Y = np.where(mask, logt - best, 0.0)
+    Y = np.where(mask, np.minimum(logt - best, TARGET_CLIP), 0.0)
     return X, T, Y, mask.astype(np.float64)
 
 
@@ -196,7 +202,8 @@ def train(paths, steps=1500, lr=3e-3, seed=7, out_dir=HERE, n_val=80, every=25):
     ev = evaluate(rows, w, mean, scale, n_val)
     ev["training"] = {"max_steps": steps, "kept_step": best_s, "lr": lr, "seed": seed,
                       "fit_tensors": [0, N_TRAIN - n_val], "validation_tensors": [N_TRAIN - n_val, N_TRAIN],
-                      "heldout_tensors": [N_TRAIN, N_TOTAL], "hidden": H, "features": F}
+                      "heldout_tensors": [N_TRAIN, N_TOTAL], "hidden": H, "features": F,
+                      "target_clip": TARGET_CLIP}
     with open(os.path.join(out_dir, os.path.basename(EVAL)), "w") as f:
         json.dump(ev, f, indent=1)
     print(json.dumps(ev["summary"]), flush=True)
