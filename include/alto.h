@@ -203,7 +203,10 @@ int alto_select(const alto_tensor *t, int mode, int R, int prec, alto_exec *out)
 int alto_selector_load(const float *weights, size_t n);
 
 /* alto_selector_features — the F = 12 selector features of (tensor, mode,
- * R, prec), written to host `out`.  Host only. */
+ * R, prec), written to host `out`: log2 I_mode, log2 nnz, log2 nnz/I_mode,
+ * N, log2 R, prec, B/32, key bits/64, log2 of the sum and of the largest of
+ * the other dims, log2 bytes of the smallest other factor matrix, and
+ * log2 I_mode*R.  Host only. */
 int alto_selector_features(const alto_tensor *t, int mode, int R, int prec, float *out);
 
 /*

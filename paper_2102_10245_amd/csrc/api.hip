@@ -245,11 +245,14 @@ size_t staged_lds_budget() {
     return budget;
 }
 
-// workgroup size of launches that flush with atomics (ALTO_MT_THREADS:
-// 64..1024, a multiple of 64)
-int atomic_threads() {
-    const long v = env_long("ALTO_MT_THREADS", 256);
-    return (v >= 64 && v <= 1024 && v % 64 == 0) ? (int)v : 256;
+// Workgroup size of launches that flush with atomics: enough waves for
+// about eight per SIMD over the whole grid of L workgroups (1024 threads at
+// L <= 512, 512 at L = 1024, 256 above).  ALTO_MT_THREADS (64..1024, a
+// multiple of 64) overrides.
+int atomic_threads(int L) {
+    const long v = env_long("ALTO_MT_THREADS", 0);
+    if (v >= 64 && v <= 1024 && v % 64 == 0) return (int)v;
+    return L <= 512 ? 1024 : (L <= 1024 ? 512 : 256);
 }
 
 // workgroup size for a staged launch whose Temp takes `bytes` of LDS
@@ -436,7 +439,7 @@ int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int p
         a.staged = staged;
         a.temp_rows = rows;
         a.threads = staged ? staged_threads((size_t)rows * temp_stride(R) * 4)
-                           : (a.dec.smask ? 1024 : atomic_threads());
+                           : (a.dec.smask ? 1024 : atomic_threads(t->part->L));
         return launch_mt(a, t->key_bits, prec, s);
     };
     if (getenv("ALTO_DEBUG_PLAN"))

@@ -246,15 +246,32 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
     };
 
     // The whole wave empties the queue: R consecutive lanes per queued row.
+    // Entries of one output row at consecutive slots (neighbouring groups
+    // that each ended a piece of the same run) are summed in slot order first,
+    // so such a run costs one atomic per wave instead of one per group.
     auto drain = [&]() {
         if constexpr (QUEUE) {
             constexpr int PER = 64 / RT;  // rows per instruction
-            for (int q0 = 0; q0 < qn; q0 += PER) {
-                const int q = q0 + lane / RT, col = lane % RT;
-                if (q < qn) {
-                    const float *e = qbuf + q * (RT + 1);
-                    const uint32_t row = __float_as_uint(e[RT]);
-                    unsafeAtomicAdd(atom + (uint64_t)row * RT + col, e[col]);
+            auto row_at = [&](int q) { return __float_as_uint(qbuf[q * (RT + 1) + RT]); };
+            bool dup = false;
+            for (int q = lane + 1; q < qn; q += 64) dup |= row_at(q) == row_at(q - 1);
+            if (__ballot(dup) == 0) {
+                for (int q0 = 0; q0 < qn; q0 += PER) {
+                    const int q = q0 + lane / RT, col = lane % RT;
+                    if (q < qn) unsafeAtomicAdd(atom + (uint64_t)row_at(q) * RT + col, qbuf[q * (RT + 1) + col]);
+                }
+            } else {
+                for (int q0 = 0; q0 < qn; q0 += PER) {
+                    const int q = q0 + lane / RT, col = lane % RT;
+                    if (q < qn) {
+                        const uint32_t row = row_at(q);
+                        if (q == 0 || row_at(q - 1) != row) {
+                            float sum = qbuf[q * (RT + 1) + col];
+                            for (int q2 = q + 1; q2 < qn && row_at(q2) == row; q2++)
+                                sum += qbuf[q2 * (RT + 1) + col];
+                            unsafeAtomicAdd(atom + (uint64_t)row * RT + col, sum);
+                        }
+                    }
                 }
             }
             qn = 0;

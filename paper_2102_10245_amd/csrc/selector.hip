@@ -29,13 +29,14 @@ Selector g_sel;
 void features(const alto_tensor *t, int mode, int R, int prec, float *f) {
     const double I = (double)t->dims[mode];
     const double M = (double)std::max<int64_t>(1, t->nnz);
-    double sum_other = 0.0, max_other = 1.0, min_reuse = 1e300;
+    double sum_other = 0.0, max_other = 1.0, min_other = 1e300;
     for (int m = 0; m < t->N; m++) {
         if (m == mode) continue;
         sum_other += (double)t->dims[m];
         max_other = std::max(max_other, (double)t->dims[m]);
-        min_reuse = std::min(min_reuse, M / (double)t->dims[m]);
+        min_other = std::min(min_other, (double)t->dims[m]);
     }
+    const double fbytes = prec == ALTO_PREC_BF16 ? 2.0 : 4.0;
     f[0] = (float)std::log2(I);
     f[1] = (float)std::log2(M);
     f[2] = (float)std::log2(M / I);
@@ -46,7 +47,7 @@ void features(const alto_tensor *t, int mode, int R, int prec, float *f) {
     f[7] = (float)t->key_bits / 64.f;
     f[8] = (float)std::log2(std::max(1.0, sum_other));
     f[9] = (float)std::log2(max_other);
-    f[10] = (float)std::log2(min_reuse);
+    f[10] = (float)std::log2(min_other * R * fbytes);  // smallest gathered factor matrix, bytes
     f[11] = (float)std::log2(I * R);
 }
 
