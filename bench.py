@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle CPU time")
     ap.add_argument("--mttkrp-only", action="store_true",
                     help="only per-mode MTTKRP repetitions of the chosen plan (for counter collection)")
+    ap.add_argument("--format", action="store_true",
+                    help="format generation and storage on every workload: alto_build time and index "
+                         "bytes vs COO (prints its own JSON line instead of the benchmark line)")
     return ap.parse_args()
 
 
@@ -54,6 +57,44 @@ def logical_bytes_per_nnz(N, R, key_bits, fbytes):
     """Algorithmic bytes one nonzero moves in a mode-n MTTKRP: its index and
     value, N-1 gathered factor rows, and its R-wide FP32 output update."""
     return key_bits / 8 + 4 + (N - 1) * R * fbytes + 4 * R
+
+
+def format_experiment(alto, torch, synth, dev, reps=3):
+    """alto_build time (encode, sort, coalesce, partition; inputs resident in
+    HBM) and stored index bytes vs uint32 COO coordinates (Eq. 1 vs the COO
+    count) for every workload."""
+    res = []
+    for name, rec in synth.WORKLOADS.items():
+        coords, vals = synth.coo(rec)
+        c_dev = torch.from_numpy(coords.view(np.int32)).to(dev)
+        v_dev = torch.from_numpy(vals).to(dev)
+        del coords, vals
+        torch.cuda.synchronize()
+        times = []
+        info = None
+        for _ in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            t = alto.AltoTensor.build(c_dev, v_dev, rec.dims)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+            info = t.info()
+            t.close()
+        ms = float(np.median(times[1:]))  # the first build also loads kernels
+        M = info["nnz"]
+        r = {"workload": name, "dims": list(rec.dims), "nnz_draws": rec.nnz, "nnz": M,
+             "index_bits": info["index_bits"], "key_bits": info["key_bits"],
+             "alto_index_bytes": info["index_bytes"], "coo_index_bytes": info["coo_index_bytes"],
+             "index_bytes_ratio_coo_over_alto": info["coo_index_bytes"] / max(1.0, info["index_bytes"]),
+             "build_ms": ms, "build_draws_per_s": rec.nnz / (ms * 1e-3)}
+        res.append(r)
+        log(f"format {name}: B={r['index_bits']} W={r['key_bits']} index {info['index_bytes'] / 1e9:.3f} GB vs "
+            f"COO {info['coo_index_bytes'] / 1e9:.3f} GB; alto_build {ms:.2f} ms "
+            f"({r['build_draws_per_s'] / 1e9:.2f} G draws/s)")
+        del c_dev, v_dev
+        torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -72,6 +113,9 @@ def main():
     alto.lib()  # fail loudly if the HIP library is missing
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.format:
+        print(json.dumps({"format_experiment": format_experiment(alto, torch, synth, dev)}))
+        return
     have_sel = (not args.no_selector) and alto.load_default_selector()
     rec = synth.WORKLOADS[args.workload]
     R = rec.rank
