@@ -237,8 +237,15 @@ int alto_mlp_adam(int64_t P, float *params, const float *grads, float *m, float 
  *                          (device, L*N*2 uint32: [l][n] = {T^s, T^e}).  Either may be NULL.
  *   alto_export_coverage:  cov_out (device, I_mode uint32): number of segments
  *                          whose mode interval holds each row.
+ *   alto_export_mode_order: the segment-local order by `mode` on the current
+ *                          partition (the order the `sorted` strategy reads;
+ *                          built now if it does not exist yet): keys_out and
+ *                          vals_out as for alto_export_keys.  Inside every
+ *                          segment the nonzeros are in increasing coordinate
+ *                          along `mode`, ties in the tensor's order.
  */
 int alto_export_keys(const alto_tensor *t, void *keys_out, float *vals_out, hipStream_t stream);
+int alto_export_mode_order(alto_tensor *t, int mode, void *keys_out, float *vals_out, hipStream_t stream);
 int alto_export_partition(const alto_tensor *t, int64_t *seg_out, uint32_t *ivl_out,
                           hipStream_t stream);
 int alto_export_coverage(const alto_tensor *t, int mode, uint32_t *cov_out, hipStream_t stream);

@@ -27,7 +27,7 @@ STRATEGY_NAME = {v: k for k, v in STRATEGY.items()}
 EXPORTS = (
     "alto_build", "alto_info", "alto_partition", "alto_mttkrp", "cp_als", "alto_select",
     "alto_selector_load", "alto_selector_features", "alto_mlp_forward", "alto_mlp_backward",
-    "alto_mlp_adam", "alto_export_keys", "alto_export_partition", "alto_export_coverage",
+    "alto_mlp_adam", "alto_export_keys", "alto_export_mode_order", "alto_export_partition", "alto_export_coverage",
     "alto_round_bf16", "alto_free", "alto_last_error", "alto_device_compute_units", "alto_layout",
 )
 
@@ -87,6 +87,7 @@ def lib():
     L.alto_mlp_adam.argtypes = [i64, vp, vp, vp, vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float, i32, vp]
     L.alto_export_keys.argtypes = [vp, vp, vp, vp]
+    L.alto_export_mode_order.argtypes = [vp, i32, vp, vp, vp]
     L.alto_export_partition.argtypes = [vp, vp, vp, vp]
     L.alto_export_coverage.argtypes = [vp, i32, vp, vp]
     L.alto_round_bf16.argtypes = [vp, vp, i64, vp]
@@ -274,6 +275,20 @@ class AltoTensor:
             keys = torch.empty((M, 2), dtype=torch.int64, device=dev)
         vals = torch.empty(M, dtype=torch.float32, device=dev)
         _check(self._lib.alto_export_keys(self._h, _ptr(keys), _ptr(vals), _stream(stream)))
+        return keys, vals
+
+    def export_mode_order(self, mode: int, stream=None):
+        """(keys, vals) of the segment-local order by `mode` (layout as export_keys)."""
+        torch = _torch()
+        inf = self.info()
+        if not 0 <= mode < inf["N"]:
+            raise ValueError("mode out of range")
+        M, kb = inf["nnz"], inf["key_bits"]
+        dev = torch.device("cuda", torch.cuda.current_device())
+        shape = (M, 2) if kb == 128 else (M,)
+        keys = torch.empty(shape, dtype=torch.int32 if kb == 32 else torch.int64, device=dev)
+        vals = torch.empty(M, dtype=torch.float32, device=dev)
+        _check(self._lib.alto_export_mode_order(self._h, mode, _ptr(keys), _ptr(vals), _stream(stream)))
         return keys, vals
 
     def export_partition(self, stream=None):

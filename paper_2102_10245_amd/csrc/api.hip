@@ -110,58 +110,21 @@ int make_layout(alto_tensor *t, int key_bits_req) {
 }
 
 // Segment-local order by one mode: inside every line segment, a stable
-// reordering of the nonzeros by their mode coordinate (radix sort of
-// (segment, row) keys carrying the position), then a gather of index and
-// values into their own arrays.  Built once per mode and partition.
+// reordering of the nonzeros by their mode coordinate, written to arrays of
+// its own (one workgroup per segment, see seg_order_k).  Built once per mode
+// and partition.
 int build_mode_order(alto_tensor *t, int mode, hipStream_t s) {
     Partition &P = *t->part;
     if (P.okeys[mode]) return ALTO_OK;
     const int64_t n = t->nnz;
-    const int L = P.L;
-    const int lbits = ceil_log2((uint64_t)std::max(1, L));
-    const int bits = lbits + t->nbits[mode];
-    const int wide = bits > 32;
-    const int okb = wide ? 64 : 32;
+    if ((uint64_t)n > 0xffffffffull) return set_error(ALTO_E_INVAL, "segment-local orders need fewer than 2^32 nonzeros");
     const size_t kb = (size_t)t->key_bits / 8;
-    void *ok = nullptr, *ok2 = nullptr;
-    uint32_t *pos = nullptr, *pos2 = nullptr;
-    int rc = ALTO_OK;
-    auto cleanup = [&]() {
-        (void)hipStreamSynchronize(s);
-        (void)hipFree(ok);
-        (void)hipFree(ok2);
-        (void)hipFree(pos);
-        (void)hipFree(pos2);
-    };
-#define ALTO_TRY2(call)                             \
-    do {                                            \
-        hipError_t e_ = (call);                     \
-        if (e_ != hipSuccess) {                     \
-            rc = hip_error(e_, #call);              \
-            cleanup();                              \
-            return rc;                              \
-        }                                           \
-    } while (0)
-    ALTO_TRY2(hipMalloc(&ok, (size_t)n * okb / 8));
-    ALTO_TRY2(hipMalloc(&ok2, (size_t)n * okb / 8));
-    ALTO_TRY2(hipMalloc(&pos, (size_t)n * 4));
-    ALTO_TRY2(hipMalloc(&pos2, (size_t)n * 4));
-    rc = launch_order_keys(t->key_bits, t->keys, P.d_seg, L, t->tab, mode, t->nbits[mode], wide, ok, pos, s);
-    if (!rc) rc = ensure_workspace(t, radix_sort_scratch(okb, n));
-    bool in_alt = false;
-    if (!rc)
-        rc = radix_sort(okb, bits, n, ok, (float *)pos, ok2, (float *)pos2, t->ws, t->ws_bytes, &in_alt, s);
-    if (rc) {
-        cleanup();
-        return rc;
-    }
-    uint32_t *perm = in_alt ? pos2 : pos;
-    ALTO_TRY2(hipMalloc(&P.okeys[mode], kb * n));
-    ALTO_TRY2(hipMalloc(&P.ovals[mode], sizeof(float) * n));
-    rc = launch_gather(t->key_bits, t->keys, t->vals, perm, n, P.okeys[mode], P.ovals[mode], s);
-    cleanup();
-#undef ALTO_TRY2
-    return rc;
+    int rc = ensure_workspace(t, (size_t)n * 4 * sizeof(uint32_t));
+    if (rc) return rc;
+    ALTO_HIP(hipMalloc(&P.okeys[mode], kb * n));
+    ALTO_HIP(hipMalloc(&P.ovals[mode], sizeof(float) * n));
+    return launch_seg_order(t->key_bits, t->keys, t->vals, P.d_seg, P.L, t->tab, mode, t->nbits[mode],
+                            (uint32_t *)t->ws, n, P.okeys[mode], P.ovals[mode], s);
 }
 
 int cu_count() {
@@ -644,6 +607,21 @@ int alto_export_keys(const alto_tensor *t, void *keys_out, float *vals_out, hipS
     if (keys_out)
         ALTO_HIP(hipMemcpyAsync(keys_out, t->keys, (size_t)t->nnz * t->key_bits / 8, hipMemcpyDeviceToDevice, s));
     if (vals_out) ALTO_HIP(hipMemcpyAsync(vals_out, t->vals, sizeof(float) * t->nnz, hipMemcpyDeviceToDevice, s));
+    return ALTO_OK;
+}
+
+int alto_export_mode_order(alto_tensor *t, int mode, void *keys_out, float *vals_out, hipStream_t s) {
+    g_err.clear();
+    int rc = check_tensor(t);
+    if (rc) return rc;
+    if (mode < 0 || mode >= t->N) return set_error(ALTO_E_INVAL, "mode out of range");
+    if (t->nnz == 0) return ALTO_OK;
+    rc = build_mode_order(t, mode, s);
+    if (rc) return rc;
+    const Partition &P = *t->part;
+    if (keys_out)
+        ALTO_HIP(hipMemcpyAsync(keys_out, P.okeys[mode], (size_t)t->nnz * t->key_bits / 8, hipMemcpyDeviceToDevice, s));
+    if (vals_out) ALTO_HIP(hipMemcpyAsync(vals_out, P.ovals[mode], sizeof(float) * t->nnz, hipMemcpyDeviceToDevice, s));
     return ALTO_OK;
 }
 

@@ -399,27 +399,127 @@ __global__ __launch_bounds__(kThreads) void intervals_k(const K *__restrict__ ke
 }
 
 // ------------------------------------------------------------ mode ordering
-// okey[x] = (segment of x) << shift | row of x along `mode`; pos[x] = x.
-template <typename K, typename OK>
-__global__ __launch_bounds__(kThreads) void order_keys_k(const K *__restrict__ keys, const int64_t *__restrict__ seg,
-                                                         RunTable tab, int mode, int shift, OK *__restrict__ okey,
-                                                         uint32_t *__restrict__ pos) {
-    const int l = blockIdx.x;
-    const int64_t b = seg[l], e = seg[l + 1];
-    for (int64_t x = b + threadIdx.x; x < e; x += kThreads) {
-        okey[x] = ((OK)l << shift) | (OK)extract_mode(keys[x], tab, mode);
-        pos[x] = (uint32_t)x;
-    }
-}
+// Segment-local order by one mode: inside every line segment, a stable
+// reordering of the nonzeros by their coordinate along `mode` (ties keep the
+// linearized order).  One 1024-thread workgroup per segment runs an LSD radix
+// sort on the coordinate's bits alone (the segment bits need no sorting), so
+// a segment's working set stays in L2 across its passes; the last pass
+// writes the reordered index and values directly.
+constexpr int kSoThreads = 1024;
+constexpr int kSoWaves = kSoThreads / 64;
+constexpr int kSoItems = 4;
+constexpr int kSoTile = kSoThreads * kSoItems;
 
 template <typename K>
-__global__ __launch_bounds__(kThreads) void gather_k(const K *__restrict__ keys, const float *__restrict__ vals,
-                                                     const uint32_t *__restrict__ pos, int64_t n, K *__restrict__ okeys,
-                                                     float *__restrict__ ovals) {
-    for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < n; x += (int64_t)gridDim.x * kThreads) {
-        const uint32_t p = pos[x];
-        okeys[x] = keys[p];
-        ovals[x] = vals[p];
+__global__ __launch_bounds__(kSoThreads) void seg_order_k(const K *__restrict__ keys, const float *__restrict__ vals,
+                                                          const int64_t *__restrict__ seg, RunTable tab, int mode,
+                                                          int nbits, uint32_t *__restrict__ rowA,
+                                                          uint32_t *__restrict__ posA, uint32_t *__restrict__ rowB,
+                                                          uint32_t *__restrict__ posB, K *__restrict__ okeys,
+                                                          float *__restrict__ ovals) {
+    __shared__ uint32_t cnt[kSoWaves][256];
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t tot[256];
+    const int64_t sb = seg[blockIdx.x], n = seg[blockIdx.x + 1] - sb;
+    const int passes = (nbits + 7) / 8;
+    const int lane = __lane_id(), wave = threadIdx.x / 64;
+    if (passes == 0) {  // a one-row mode: the order is the linearized one
+        for (int64_t i = threadIdx.x; i < n; i += kSoThreads) {
+            okeys[sb + i] = keys[sb + i];
+            ovals[sb + i] = vals[sb + i];
+        }
+        return;
+    }
+    for (int64_t i = threadIdx.x; i < n; i += kSoThreads) {
+        rowA[sb + i] = extract_mode(keys[sb + i], tab, mode);
+        posA[sb + i] = (uint32_t)(sb + i);
+    }
+    __syncthreads();
+    uint32_t *srow = rowA, *spos = posA, *drow = rowB, *dpos = posB;
+    const uint64_t lt = lanemask_lt();
+    for (int p = 0; p < passes; p++) {
+        const int shift = 8 * p;
+        const bool last = p == passes - 1;
+        // digit histogram of the segment, then its exclusive scan
+        if (threadIdx.x < 256) tot[threadIdx.x] = 0;
+        __syncthreads();
+        for (int64_t i = threadIdx.x; i < n; i += kSoThreads) atomicAdd(&tot[(srow[sb + i] >> shift) & 255u], 1u);
+        __syncthreads();
+        if (wave == 0) {
+            uint32_t v[4], sum = 0;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                v[q] = tot[lane * 4 + q];
+                sum += v[q];
+            }
+            uint32_t inc = sum;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = (uint32_t)__shfl_up((int)inc, off);
+                if (lane >= off) inc += y;
+            }
+            uint32_t run = inc - sum;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                base[lane * 4 + q] = run;
+                run += v[q];
+            }
+        }
+        __syncthreads();
+        // stable scatter, one tile at a time in input order: within a tile,
+        // wave w owns items [w*64*I, (w+1)*64*I), item j of a lane is
+        // w*64*I + j*64 + lane
+        for (int64_t t0 = 0; t0 < n; t0 += kSoTile) {
+            for (int q = threadIdx.x; q < kSoWaves * 256; q += kSoThreads) (&cnt[0][0])[q] = 0;
+            __syncthreads();
+            uint32_t r[kSoItems], ps[kSoItems], dg[kSoItems], rk[kSoItems];
+#pragma unroll
+            for (int j = 0; j < kSoItems; j++) {
+                const int64_t x = t0 + (int64_t)wave * 64 * kSoItems + j * 64 + lane;
+                const bool valid = x < n;
+                r[j] = valid ? srow[sb + x] : 0u;
+                ps[j] = valid ? spos[sb + x] : 0u;
+                const uint32_t d = (r[j] >> shift) & 255u;
+                const uint64_t m = match_digit(d, valid);
+                const uint32_t before = cnt[wave][d];  // every lane reads before the leader writes
+                rk[j] = before + (uint32_t)__builtin_popcountll(m & lt);
+                dg[j] = valid ? d : 0xffffffffu;
+                __builtin_amdgcn_wave_barrier();
+                if (valid && lane == (int)__builtin_ctzll(m)) cnt[wave][d] = before + (uint32_t)__builtin_popcountll(m);
+                __builtin_amdgcn_wave_barrier();
+            }
+            __syncthreads();
+            if (threadIdx.x < 256) {
+                uint32_t run = 0;
+#pragma unroll
+                for (int w = 0; w < kSoWaves; w++) {
+                    const uint32_t c = cnt[w][threadIdx.x];
+                    cnt[w][threadIdx.x] = run;
+                    run += c;
+                }
+                tot[threadIdx.x] = run;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < kSoItems; j++) {
+                if (dg[j] == 0xffffffffu) continue;
+                const int64_t dst = sb + base[dg[j]] + cnt[wave][dg[j]] + rk[j];
+                if (last) {
+                    okeys[dst] = keys[ps[j]];
+                    ovals[dst] = vals[ps[j]];
+                } else {
+                    drow[dst] = r[j];
+                    dpos[dst] = ps[j];
+                }
+            }
+            __syncthreads();
+            if (threadIdx.x < 256) base[threadIdx.x] += tot[threadIdx.x];
+            __syncthreads();
+        }
+        uint32_t *tr = srow, *tp = spos;
+        srow = drow;
+        spos = dpos;
+        drow = tr;
+        dpos = tp;
     }
 }
 
@@ -563,30 +663,18 @@ int coverage(int N, int L, const uint32_t *d_ivl, int mode, uint64_t dim, uint32
     return device_scan<int32_t, int32_t, true>(diff, (int32_t *)cov, (int64_t)dim, nullptr, scan_ws, s);
 }
 
-int launch_order_keys(int key_bits, const void *keys, const int64_t *seg, int L, const RunTable &tab, int mode,
-                      int shift, int wide, void *okey, uint32_t *pos, hipStream_t s) {
-    if (L <= 0) return ALTO_OK;
-#define ALTO_OK_(K, OK) \
-    order_keys_k<K, OK><<<L, kThreads, 0, s>>>((const K *)keys, seg, tab, mode, shift, (OK *)okey, pos)
-    if (key_bits == 32) {
-        if (wide) ALTO_OK_(uint32_t, uint64_t); else ALTO_OK_(uint32_t, uint32_t);
-    } else if (key_bits == 64) {
-        if (wide) ALTO_OK_(uint64_t, uint64_t); else ALTO_OK_(uint64_t, uint32_t);
-    } else {
-        if (wide) ALTO_OK_(u128, uint64_t); else ALTO_OK_(u128, uint32_t);
-    }
-#undef ALTO_OK_
-    ALTO_HIP(hipGetLastError());
-    return ALTO_OK;
-}
-
-int launch_gather(int key_bits, const void *keys, const float *vals, const uint32_t *pos, int64_t n, void *okeys,
-                  float *ovals, hipStream_t s) {
-    if (n <= 0) return ALTO_OK;
-    const unsigned g = grid_for(n, kThreads * 4);
-    if (key_bits == 32) gather_k<uint32_t><<<g, kThreads, 0, s>>>((const uint32_t *)keys, vals, pos, n, (uint32_t *)okeys, ovals);
-    else if (key_bits == 64) gather_k<uint64_t><<<g, kThreads, 0, s>>>((const uint64_t *)keys, vals, pos, n, (uint64_t *)okeys, ovals);
-    else gather_k<u128><<<g, kThreads, 0, s>>>((const u128 *)keys, vals, pos, n, (u128 *)okeys, ovals);
+int launch_seg_order(int key_bits, const void *keys, const float *vals, const int64_t *seg, int L,
+                     const RunTable &tab, int mode, int nbits, uint32_t *scratch, int64_t n, void *okeys,
+                     float *ovals, hipStream_t s) {
+    if (L <= 0 || n <= 0) return ALTO_OK;
+    uint32_t *rowA = scratch, *posA = scratch + n, *rowB = scratch + 2 * n, *posB = scratch + 3 * n;
+#define ALTO_SO_(K)                                                                                          \
+    seg_order_k<K><<<L, kSoThreads, 0, s>>>((const K *)keys, vals, seg, tab, mode, nbits, rowA, posA, rowB, \
+                                            posB, (K *)okeys, ovals)
+    if (key_bits == 32) ALTO_SO_(uint32_t);
+    else if (key_bits == 64) ALTO_SO_(uint64_t);
+    else ALTO_SO_(u128);
+#undef ALTO_SO_
     ALTO_HIP(hipGetLastError());
     return ALTO_OK;
 }

@@ -215,10 +215,10 @@ int coverage(int N, int L, const uint32_t *d_ivl, int mode, uint64_t dim, uint32
              size_t scratch_bytes, hipStream_t s);
 size_t coverage_scratch(uint64_t dim);
 int launch_sumsq(const float *vals, int64_t n, double *out, hipStream_t s);
-int launch_order_keys(int key_bits, const void *keys, const int64_t *seg, int L, const RunTable &tab, int mode,
-                      int shift, int wide, void *okey, uint32_t *pos, hipStream_t s);
-int launch_gather(int key_bits, const void *keys, const float *vals, const uint32_t *pos, int64_t n, void *okeys,
-                  float *ovals, hipStream_t s);
+// segment-local order by `mode` (scratch: 4*n uint32)
+int launch_seg_order(int key_bits, const void *keys, const float *vals, const int64_t *seg, int L,
+                     const RunTable &tab, int mode, int nbits, uint32_t *scratch, int64_t n, void *okeys,
+                     float *ovals, hipStream_t s);
 
 
 // cpals.hip

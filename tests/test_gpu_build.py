@@ -128,3 +128,36 @@ def test_bf16_rounding_bits_match_oracle():
     got = alto.round_bf16(torch.from_numpy(x).cuda()).cpu().numpy().view(np.uint16)
     ref, _ = oracle.bf16_round(x)
     assert np.array_equal(got, ref)
+
+
+# segment-local mode orders (the `sorted` strategy's input): every key width,
+# an order-5 tensor with one-row modes, and segments longer than one
+# workgroup tile of 4096 nonzeros
+ORDER_CASES = [CASES[2], CASES[4], CASES[5], CASES[6],
+               (synth.Recipe("long_segments", (3000, 700, 90), 120_000, (1.1, 0.6, 0), seed=8), 0, 7)]
+
+
+@pytest.mark.parametrize("rec,kb,L", ORDER_CASES, ids=[c[0].name for c in ORDER_CASES])
+def test_mode_order_bit_exact(rec, kb, L):
+    print("case", rec.name, rec.dims, rec.nnz, kb, L, flush=True)
+    coords, vals = synth.coo(rec)
+    c, v = to_dev(coords, vals)
+    t = alto.AltoTensor.build(c, v, rec.dims, key_bits=kb, num_segments=L)
+    info = t.info()
+    (olo, ohi), ov, lay, _ = oracle_alto(rec.dims, coords, vals)
+    M = len(olo)
+    oseg = oracle.partition(M, L)
+    segid = np.repeat(np.arange(len(oseg) - 1), np.diff(oseg))
+    oc = oracle.decode(lay, (olo, ohi))
+    for n in range(len(rec.dims)):
+        # stable by (segment, coordinate along n): ties keep the linearized order
+        perm = np.lexsort((np.arange(M), oc[n], segid))
+        keys, gv = t.export_mode_order(n)
+        glo, ghi = keys_numpy(keys, info["key_bits"])
+        assert np.array_equal(glo, olo[perm]) and np.array_equal(ghi, ohi[perm]), n
+        gv = gv.cpu().numpy().astype(np.float64)
+        if info["nnz"] == rec.nnz:
+            assert np.array_equal(gv, ov[perm]), n
+        else:
+            assert np.allclose(gv, ov[perm], rtol=2e-6, atol=0), n
+    t.close()
