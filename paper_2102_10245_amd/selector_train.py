@@ -53,7 +53,7 @@ def candidate(k):
 
 def recipe(i):
     """The i-th corpus tensor: 3-5 modes, dims log-uniform in [1e2, 1e7],
-    nnz log-uniform in [1e6, 5e7] (at most half of the index space), Zipf
+    nnz log-uniform in [1e6, 2e8] (at most half of the index space), Zipf
     exponent uniform in [0, 1.5] per mode, R in {8, 16, 32, 64}, FP32 or
     BF16 factors."""
     import synth
@@ -61,7 +61,7 @@ def recipe(i):
     N = int(rng.integers(3, 6))
     dims = tuple(int(round(10 ** rng.uniform(2, 7))) for _ in range(N))
     space = math.prod(float(d) for d in dims)
-    nnz = int(min(10 ** rng.uniform(6, math.log10(5e7)), 0.5 * space))
+    nnz = int(min(10 ** rng.uniform(6, math.log10(2e8)), 0.5 * space))
     zipf = tuple(float(rng.uniform(0, 1.5)) for _ in range(N))
     R = int(rng.choice([8, 16, 32, 64]))
     prec = "bf16" if rng.random() < 0.5 else "f32"
