@@ -119,12 +119,12 @@ int build_mode_order(alto_tensor *t, int mode, hipStream_t s) {
     const int64_t n = t->nnz;
     if ((uint64_t)n > 0xffffffffull) return set_error(ALTO_E_INVAL, "segment-local orders need fewer than 2^32 nonzeros");
     const size_t kb = (size_t)t->key_bits / 8;
-    int rc = ensure_workspace(t, (size_t)n * 4 * sizeof(uint32_t));
+    int rc = ensure_workspace(t, seg_order_scratch(t->key_bits, n));
     if (rc) return rc;
     ALTO_HIP(hipMalloc(&P.okeys[mode], kb * n));
     ALTO_HIP(hipMalloc(&P.ovals[mode], sizeof(float) * n));
-    return launch_seg_order(t->key_bits, t->keys, t->vals, P.d_seg, P.L, t->tab, mode, t->nbits[mode],
-                            (uint32_t *)t->ws, n, P.okeys[mode], P.ovals[mode], s);
+    return launch_seg_order(t->key_bits, t->keys, t->vals, P.d_seg, P.L, t->tab, t->ctab, mode, t->nbits[mode],
+                            t->ws, n, P.okeys[mode], P.ovals[mode], s);
 }
 
 int cu_count() {
@@ -147,7 +147,7 @@ int build_partition(alto_tensor *t, int Le, hipStream_t s, std::unique_ptr<Parti
     ALTO_HIP(hipMalloc(&p.d_seg, sizeof(int64_t) * (Le + 1)));
     ALTO_HIP(hipMalloc(&p.d_ivl, sizeof(uint32_t) * std::max(1, Le * t->N * 2)));
     ALTO_HIP(hipMemcpyAsync(p.d_seg, p.h_seg.data(), sizeof(int64_t) * (Le + 1), hipMemcpyHostToDevice, s));
-    int rc = launch_intervals(t->key_bits, t->keys, p.d_seg, Le, t->tab, p.d_ivl, s);
+    int rc = launch_intervals(t->key_bits, t->keys, p.d_seg, Le, t->tab, t->ctab, p.d_ivl, s);
     if (rc) return rc;
     uint64_t maxdim = 0;
     for (int n = 0; n < t->N; n++) maxdim = std::max(maxdim, t->dims[n]);

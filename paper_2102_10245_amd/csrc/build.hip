@@ -351,11 +351,18 @@ __global__ __launch_bounds__(kThreads) void compact_k(const K *__restrict__ keys
 // ------------------------------------------------------------ intervals
 template <typename K>
 __global__ __launch_bounds__(kThreads) void intervals_k(const K *__restrict__ keys, const int64_t *__restrict__ seg,
-                                                        RunTable tab, uint32_t *__restrict__ ivl) {
+                                                        RunTable tab, const K *__restrict__ ctab,
+                                                        uint32_t *__restrict__ ivl) {
+    constexpr int kTab = byte_table_entries(8 * (int)sizeof(K));
     __shared__ uint32_t smn[kWaves][kMaxModes], smx[kWaves][kMaxModes];
+    __shared__ K ltab[kTab > 0 ? kTab : 1];
     const int l = blockIdx.x;
     const int N = tab.N;
     const int64_t b = seg[l], e = seg[l + 1];
+    if constexpr (kTab > 0) {
+        for (int q = threadIdx.x; q < kTab; q += kThreads) ltab[q] = ctab[q];
+        __syncthreads();
+    }
     uint32_t mn[kMaxModes], mx[kMaxModes];
 #pragma unroll
     for (int m = 0; m < kMaxModes; m++) {
@@ -364,10 +371,14 @@ __global__ __launch_bounds__(kThreads) void intervals_k(const K *__restrict__ ke
     }
     for (int64_t x = b + threadIdx.x; x < e; x += kThreads) {
         const K key = keys[x];
+        K cw{};
+        if constexpr (kTab > 0) cw = compact_index(key, ltab);
 #pragma unroll
         for (int m = 0; m < kMaxModes; m++) {
             if (m >= N) break;
-            const uint32_t c = extract_mode(key, tab, m);
+            uint32_t c;
+            if constexpr (kTab > 0) c = (uint32_t)(cw >> tab.coff[m]) & tab.cmask[m];
+            else c = extract_mode(key, tab, m);
             mn[m] = min(mn[m], c);
             mx[m] = max(mx[m], c);
         }
@@ -402,24 +413,65 @@ __global__ __launch_bounds__(kThreads) void intervals_k(const K *__restrict__ ke
 // Segment-local order by one mode: inside every line segment, a stable
 // reordering of the nonzeros by their coordinate along `mode` (ties keep the
 // linearized order).  One 1024-thread workgroup per segment runs an LSD radix
-// sort on the coordinate's bits alone (the segment bits need no sorting), so
-// a segment's working set stays in L2 across its passes; the last pass
-// writes the reordered index and values directly.
+// sort on the coordinate's bits alone (the segments are already contiguous)
+// with the index and value as payload: every pass reads its input in order
+// and writes runs of one digit contiguously after reordering a tile in LDS,
+// and the last pass lands in the output arrays.
 constexpr int kSoThreads = 1024;
 constexpr int kSoWaves = kSoThreads / 64;
 constexpr int kSoItems = 4;
 constexpr int kSoTile = kSoThreads * kSoItems;
 
 template <typename K>
+constexpr size_t seg_order_lds() {
+    return (size_t)kSoTile * (sizeof(uint32_t) + sizeof(K) + sizeof(float));
+}
+
+__device__ __forceinline__ uint32_t wave_exclusive_scan256(const uint32_t *in, uint32_t *out, int lane) {
+    uint32_t v[4], sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        v[q] = in[lane * 4 + q];
+        sum += v[q];
+    }
+    uint32_t inc = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)inc, off);
+        if (lane >= off) inc += y;
+    }
+    uint32_t run = inc - sum;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        out[lane * 4 + q] = run;
+        run += v[q];
+    }
+    return run;
+}
+
+// Buffers: rows R[2][n]; index and values alternate between the output
+// (okeys, ovals) and one scratch pair (ks, vs), chosen so that the last pass
+// writes the output.
+template <typename K>
 __global__ __launch_bounds__(kSoThreads) void seg_order_k(const K *__restrict__ keys, const float *__restrict__ vals,
-                                                          const int64_t *__restrict__ seg, RunTable tab, int mode,
-                                                          int nbits, uint32_t *__restrict__ rowA,
-                                                          uint32_t *__restrict__ posA, uint32_t *__restrict__ rowB,
-                                                          uint32_t *__restrict__ posB, K *__restrict__ okeys,
-                                                          float *__restrict__ ovals) {
+                                                          const int64_t *__restrict__ seg, RunTable tab,
+                                                          const K *__restrict__ ctab, int mode, int nbits,
+                                                          uint32_t *__restrict__ R0, uint32_t *__restrict__ R1,
+                                                          K *__restrict__ ks, float *__restrict__ vs,
+                                                          K *__restrict__ okeys, float *__restrict__ ovals) {
+    constexpr int kTab = byte_table_entries(8 * (int)sizeof(K));
+    static_assert(kTab * sizeof(K) <= seg_order_lds<K>(), "byte tables fit the staging buffer");
     __shared__ uint32_t cnt[kSoWaves][256];
     __shared__ uint32_t base[256];
     __shared__ uint32_t tot[256];
+    __shared__ uint32_t tstart[256];
+    __shared__ uint32_t hist[256];
+    // staging of one tile in digit order; the byte tables use the same memory
+    // while the rows are decoded
+    extern __shared__ __align__(16) char dyn[];
+    K *const ltab = reinterpret_cast<K *>(dyn);
+    K *const sk = reinterpret_cast<K *>(dyn);
+    uint32_t *const sr = reinterpret_cast<uint32_t *>(dyn + (size_t)kSoTile * sizeof(K));
+    float *const sv = reinterpret_cast<float *>(dyn + (size_t)kSoTile * (sizeof(K) + sizeof(uint32_t)));
     const int64_t sb = seg[blockIdx.x], n = seg[blockIdx.x + 1] - sb;
     const int passes = (nbits + 7) / 8;
     const int lane = __lane_id(), wave = threadIdx.x / 64;
@@ -430,54 +482,72 @@ __global__ __launch_bounds__(kSoThreads) void seg_order_k(const K *__restrict__ 
         }
         return;
     }
-    for (int64_t i = threadIdx.x; i < n; i += kSoThreads) {
-        rowA[sb + i] = extract_mode(keys[sb + i], tab, mode);
-        posA[sb + i] = (uint32_t)(sb + i);
+    // pass p reads (R[p&1], D_p) and writes (R[(p+1)&1], D_{p+1}), D_passes = output
+    K *Dk[2] = {okeys, ks};
+    float *Dv[2] = {ovals, vs};
+    // D_p is the output when passes - p is even
+    auto dk = [&](int p) { return Dk[(passes - p) & 1]; };
+    auto dv = [&](int p) { return Dv[(passes - p) & 1]; };
+    uint32_t *Rr[2] = {R0, R1};
+    // decode the rows into the pass-0 input; the histogram of the first digit on the way
+    if (threadIdx.x < 256) hist[threadIdx.x] = 0;
+    if constexpr (kTab > 0)
+        for (int q = threadIdx.x; q < kTab; q += kSoThreads) ltab[q] = ctab[q];
+    __syncthreads();
+    {
+        K *k0 = dk(0);
+        float *v0 = dv(0);
+        for (int64_t i = threadIdx.x; i < n; i += kSoThreads) {
+            const K key = keys[sb + i];
+            uint32_t row;
+            if constexpr (kTab > 0) row = (uint32_t)(compact_index(key, ltab) >> tab.coff[mode]) & tab.cmask[mode];
+            else row = extract_mode(key, tab, mode);
+            Rr[0][sb + i] = row;
+            k0[sb + i] = key;
+            v0[sb + i] = vals[sb + i];
+            atomicAdd(&hist[row & 255u], 1u);
+        }
     }
     __syncthreads();
-    uint32_t *srow = rowA, *spos = posA, *drow = rowB, *dpos = posB;
     const uint64_t lt = lanemask_lt();
     for (int p = 0; p < passes; p++) {
         const int shift = 8 * p;
         const bool last = p == passes - 1;
-        // digit histogram of the segment, then its exclusive scan
-        if (threadIdx.x < 256) tot[threadIdx.x] = 0;
-        __syncthreads();
-        for (int64_t i = threadIdx.x; i < n; i += kSoThreads) atomicAdd(&tot[(srow[sb + i] >> shift) & 255u], 1u);
-        __syncthreads();
+        const uint32_t *srow = Rr[p & 1];
+        uint32_t *drow = Rr[(p + 1) & 1];
+        const K *skey = dk(p);
+        const float *sval = dv(p);
+        K *dkey = dk(p + 1);
+        float *dval = dv(p + 1);
+        // exclusive scan of this digit's histogram; the next digit's is
+        // counted while this pass writes
         if (wave == 0) {
-            uint32_t v[4], sum = 0;
+            wave_exclusive_scan256(hist, base, lane);
 #pragma unroll
-            for (int q = 0; q < 4; q++) {
-                v[q] = tot[lane * 4 + q];
-                sum += v[q];
-            }
-            uint32_t inc = sum;
-            for (int off = 1; off < 64; off <<= 1) {
-                const uint32_t y = (uint32_t)__shfl_up((int)inc, off);
-                if (lane >= off) inc += y;
-            }
-            uint32_t run = inc - sum;
-#pragma unroll
-            for (int q = 0; q < 4; q++) {
-                base[lane * 4 + q] = run;
-                run += v[q];
-            }
+            for (int q = 0; q < 4; q++) hist[lane * 4 + q] = 0;
         }
         __syncthreads();
         // stable scatter, one tile at a time in input order: within a tile,
         // wave w owns items [w*64*I, (w+1)*64*I), item j of a lane is
         // w*64*I + j*64 + lane
         for (int64_t t0 = 0; t0 < n; t0 += kSoTile) {
-            for (int q = threadIdx.x; q < kSoWaves * 256; q += kSoThreads) (&cnt[0][0])[q] = 0;
-            __syncthreads();
-            uint32_t r[kSoItems], ps[kSoItems], dg[kSoItems], rk[kSoItems];
+            uint32_t r[kSoItems], dg[kSoItems], rk[kSoItems];
+            K kk[kSoItems];
+            float vv[kSoItems];
 #pragma unroll
             for (int j = 0; j < kSoItems; j++) {
                 const int64_t x = t0 + (int64_t)wave * 64 * kSoItems + j * 64 + lane;
                 const bool valid = x < n;
                 r[j] = valid ? srow[sb + x] : 0u;
-                ps[j] = valid ? spos[sb + x] : 0u;
+                kk[j] = valid ? skey[sb + x] : KeyOps<K>::zero();
+                vv[j] = valid ? sval[sb + x] : 0.f;
+            }
+            for (int q = threadIdx.x; q < kSoWaves * 256; q += kSoThreads) (&cnt[0][0])[q] = 0;
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < kSoItems; j++) {
+                const int64_t x = t0 + (int64_t)wave * 64 * kSoItems + j * 64 + lane;
+                const bool valid = x < n;
                 const uint32_t d = (r[j] >> shift) & 255u;
                 const uint64_t m = match_digit(d, valid);
                 const uint32_t before = cnt[wave][d];  // every lane reads before the leader writes
@@ -499,27 +569,34 @@ __global__ __launch_bounds__(kSoThreads) void seg_order_k(const K *__restrict__ 
                 tot[threadIdx.x] = run;
             }
             __syncthreads();
+            if (wave == 0) wave_exclusive_scan256(tot, tstart, lane);  // tile-local start of every digit
+            __syncthreads();
+            // the tile in digit order in LDS, then runs of one digit written out contiguously
 #pragma unroll
             for (int j = 0; j < kSoItems; j++) {
                 if (dg[j] == 0xffffffffu) continue;
-                const int64_t dst = sb + base[dg[j]] + cnt[wave][dg[j]] + rk[j];
-                if (last) {
-                    okeys[dst] = keys[ps[j]];
-                    ovals[dst] = vals[ps[j]];
-                } else {
-                    drow[dst] = r[j];
-                    dpos[dst] = ps[j];
+                const uint32_t lp = tstart[dg[j]] + cnt[wave][dg[j]] + rk[j];
+                sr[lp] = r[j];
+                sk[lp] = kk[j];
+                sv[lp] = vv[j];
+            }
+            __syncthreads();
+            const int tn = (int)min((int64_t)kSoTile, n - t0);
+            for (int i = threadIdx.x; i < tn; i += kSoThreads) {
+                const uint32_t row = sr[i];
+                const uint32_t d = (row >> shift) & 255u;
+                const int64_t dst = sb + base[d] + (uint32_t)i - tstart[d];
+                dkey[dst] = sk[i];
+                dval[dst] = sv[i];
+                if (!last) {
+                    drow[dst] = row;
+                    atomicAdd(&hist[(row >> (shift + 8)) & 255u], 1u);
                 }
             }
             __syncthreads();
             if (threadIdx.x < 256) base[threadIdx.x] += tot[threadIdx.x];
             __syncthreads();
         }
-        uint32_t *tr = srow, *tp = spos;
-        srow = drow;
-        spos = dpos;
-        drow = tr;
-        dpos = tp;
     }
 }
 
@@ -636,12 +713,15 @@ int coalesce(int key_bits, int64_t n, const void *keys, const float *vals, void 
     return ALTO_OK;
 }
 
-int launch_intervals(int key_bits, const void *keys, const int64_t *seg, int L, const RunTable &tab, uint32_t *ivl,
-                     hipStream_t s) {
+int launch_intervals(int key_bits, const void *keys, const int64_t *seg, int L, const RunTable &tab,
+                     const void *ctab, uint32_t *ivl, hipStream_t s) {
     if (L <= 0) return ALTO_OK;
-    if (key_bits == 32) intervals_k<uint32_t><<<L, kThreads, 0, s>>>((const uint32_t *)keys, seg, tab, ivl);
-    else if (key_bits == 64) intervals_k<uint64_t><<<L, kThreads, 0, s>>>((const uint64_t *)keys, seg, tab, ivl);
-    else intervals_k<u128><<<L, kThreads, 0, s>>>((const u128 *)keys, seg, tab, ivl);
+    if (key_bits <= 64 && !ctab) return set_error(ALTO_E_INVAL, "internal: missing byte tables");
+    if (key_bits == 32)
+        intervals_k<uint32_t><<<L, kThreads, 0, s>>>((const uint32_t *)keys, seg, tab, (const uint32_t *)ctab, ivl);
+    else if (key_bits == 64)
+        intervals_k<uint64_t><<<L, kThreads, 0, s>>>((const uint64_t *)keys, seg, tab, (const uint64_t *)ctab, ivl);
+    else intervals_k<u128><<<L, kThreads, 0, s>>>((const u128 *)keys, seg, tab, nullptr, ivl);
     ALTO_HIP(hipGetLastError());
     return ALTO_OK;
 }
@@ -663,14 +743,33 @@ int coverage(int N, int L, const uint32_t *d_ivl, int mode, uint64_t dim, uint32
     return device_scan<int32_t, int32_t, true>(diff, (int32_t *)cov, (int64_t)dim, nullptr, scan_ws, s);
 }
 
+size_t seg_order_scratch(int key_bits, int64_t n) {
+    // two row arrays, one index array and one value array
+    return (size_t)n * (2 * sizeof(uint32_t) + key_bits / 8 + sizeof(float)) + 1024;
+}
+
 int launch_seg_order(int key_bits, const void *keys, const float *vals, const int64_t *seg, int L,
-                     const RunTable &tab, int mode, int nbits, uint32_t *scratch, int64_t n, void *okeys,
-                     float *ovals, hipStream_t s) {
+                     const RunTable &tab, const void *ctab, int mode, int nbits, void *scratch, int64_t n,
+                     void *okeys, float *ovals, hipStream_t s) {
     if (L <= 0 || n <= 0) return ALTO_OK;
-    uint32_t *rowA = scratch, *posA = scratch + n, *rowB = scratch + 2 * n, *posB = scratch + 3 * n;
-#define ALTO_SO_(K)                                                                                          \
-    seg_order_k<K><<<L, kSoThreads, 0, s>>>((const K *)keys, vals, seg, tab, mode, nbits, rowA, posA, rowB, \
-                                            posB, (K *)okeys, ovals)
+    if (key_bits <= 64 && !ctab) return set_error(ALTO_E_INVAL, "internal: missing byte tables");
+    auto align = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    char *p = (char *)scratch;
+    uint32_t *R0 = (uint32_t *)p;
+    uint32_t *R1 = (uint32_t *)(p + align((size_t)n * 4));
+    void *ks = p + 2 * align((size_t)n * 4);
+    float *vs = (float *)(p + 2 * align((size_t)n * 4) + align((size_t)n * key_bits / 8));
+#define ALTO_SO_(K)                                                                                              \
+    do {                                                                                                         \
+        const size_t lds = seg_order_lds<K>();                                                                   \
+        if (lds > 64 * 1024) {                                                                                   \
+            hipError_t e = hipFuncSetAttribute((const void *)seg_order_k<K>,                                     \
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);            \
+            if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute(MaxDynamicSharedMemorySize)");        \
+        }                                                                                                        \
+        seg_order_k<K><<<L, kSoThreads, lds, s>>>((const K *)keys, vals, seg, tab, (const K *)ctab, mode, nbits, \
+                                                  R0, R1, (K *)ks, vs, (K *)okeys, ovals);                       \
+    } while (0)
     if (key_bits == 32) ALTO_SO_(uint32_t);
     else if (key_bits == 64) ALTO_SO_(uint64_t);
     else ALTO_SO_(u128);

@@ -210,15 +210,16 @@ int coalesce(int key_bits, int64_t n, const void *keys, const float *vals, void 
              void *scratch, size_t scratch_bytes, int64_t *n_unique, hipStream_t s);
 size_t coalesce_scratch(int64_t n);
 int launch_intervals(int key_bits, const void *keys, const int64_t *seg, int L, const RunTable &tab,
-                     uint32_t *ivl, hipStream_t s);
+                     const void *ctab, uint32_t *ivl, hipStream_t s);
 int coverage(int N, int L, const uint32_t *d_ivl, int mode, uint64_t dim, uint32_t *cov, void *scratch,
              size_t scratch_bytes, hipStream_t s);
 size_t coverage_scratch(uint64_t dim);
 int launch_sumsq(const float *vals, int64_t n, double *out, hipStream_t s);
-// segment-local order by `mode` (scratch: 4*n uint32)
+// segment-local order by `mode` (scratch: seg_order_scratch bytes)
+size_t seg_order_scratch(int key_bits, int64_t n);
 int launch_seg_order(int key_bits, const void *keys, const float *vals, const int64_t *seg, int L,
-                     const RunTable &tab, int mode, int nbits, uint32_t *scratch, int64_t n, void *okeys,
-                     float *ovals, hipStream_t s);
+                     const RunTable &tab, const void *ctab, int mode, int nbits, void *scratch, int64_t n,
+                     void *okeys, float *ovals, hipStream_t s);
 
 
 // cpals.hip
