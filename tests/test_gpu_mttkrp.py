@@ -25,6 +25,11 @@ CASES = [
     (synth.Recipe("generic_r100_order6", (20, 18, 16, 14, 12, 10), 40_000, (0.7,) * 6, seed=24), 100, 77),
     (synth.Recipe("r256", (400, 300, 20), 20_000, (0, 0.8, 0), seed=25), 256, 0),
     (synth.Recipe("unit_modes", (1, 700, 1, 90), 30_000, (0, 1.1, 0, 0), seed=26), 16, 0),
+    # segments of at least 64K nonzeros: factor matrices of 500 rows (R = 32)
+    # and of 600 rows (R = 16) are gathered from LDS in 1024-thread workgroups
+    (small("zipf4_1Mx100kx10kx500_150M", 400_000), 32, 3),
+    (synth.Recipe("uniform3_staged_r16", (1000, 800, 600), 300_000, (), seed=27), 16, 4),
+    (synth.Recipe("staged_r64", (3000, 2000, 200), 200_000, (1.1, 0.5, 0), seed=28), 64, 2),
 ]
 
 
