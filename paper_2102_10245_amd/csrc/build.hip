@@ -146,14 +146,41 @@ __global__ __launch_bounds__(kThreads) void encode_k(CoordPtrs c, const uint64_t
 
 // ------------------------------------------------------------ radix sort
 // Stable LSD radix sort, 8-bit digits.  Each block owns one tile of
-// kThreads*ITEMS keys, split into four wave chunks of 64*ITEMS keys; inside
-// a wave, item j covers keys j*64 .. j*64+63 of the chunk.  A key's rank
-// among equal digits comes from a ballot match over the 64 lanes plus a
+// threads*ITEMS keys, split into one chunk of 64*ITEMS keys per wave;
+// inside a wave, item j covers keys j*64 .. j*64+63 of the chunk.  A key's
+// rank among equal digits comes from a ballot match over the 64 lanes plus a
 // per-wave running counter, which keeps input order (stability) without
 // atomics.
+
+// Exclusive scan of 256 counters by one wave (4 per lane); returns the total.
+__device__ __forceinline__ uint32_t wave_exclusive_scan256(const uint32_t *in, uint32_t *out, int lane) {
+    uint32_t v[4], sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        v[q] = in[lane * 4 + q];
+        sum += v[q];
+    }
+    uint32_t inc = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)inc, off);
+        if (lane >= off) inc += y;
+    }
+    uint32_t run = inc - sum;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        out[lane * 4 + q] = run;
+        run += v[q];
+    }
+    return run;
+}
+
+// 512-thread blocks for keys of up to 64 bits, 256 for 128-bit keys (whose
+// tile would otherwise not leave room for two blocks per CU)
 template <typename K>
 struct SortCfg {
-    static constexpr int kItems = sizeof(K) > 8 ? 8 : 16;
+    static constexpr int kThreads = sizeof(K) > 8 ? 256 : 512;
+    static constexpr int kWaves = kThreads / 64;
+    static constexpr int kItems = 8;
     static constexpr int kTile = kThreads * kItems;
 };
 
@@ -169,11 +196,11 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
 }
 
 template <typename K>
-__global__ __launch_bounds__(kThreads) void rs_hist_k(const K *__restrict__ keys, int64_t n, int shift,
-                                                      uint32_t *__restrict__ hist, int64_t T) {
-    constexpr int I = SortCfg<K>::kItems;
-    __shared__ uint32_t cnt[kWaves][256];
-    for (int q = threadIdx.x; q < kWaves * 256; q += kThreads) (&cnt[0][0])[q] = 0;
+__global__ __launch_bounds__(SortCfg<K>::kThreads) void rs_hist_k(const K *__restrict__ keys, int64_t n, int shift,
+                                                                   uint32_t *__restrict__ hist, int64_t T) {
+    constexpr int I = SortCfg<K>::kItems, NT = SortCfg<K>::kThreads, NW = SortCfg<K>::kWaves;
+    __shared__ uint32_t cnt[NW][256];
+    for (int q = threadIdx.x; q < NW * 256; q += NT) (&cnt[0][0])[q] = 0;
     __syncthreads();
     const int lane = __lane_id(), wave = threadIdx.x / 64;
     const int64_t base = (int64_t)blockIdx.x * SortCfg<K>::kTile + (int64_t)wave * 64 * I;
@@ -186,26 +213,28 @@ __global__ __launch_bounds__(kThreads) void rs_hist_k(const K *__restrict__ keys
     }
     __syncthreads();
     const int d = threadIdx.x;
-    uint32_t tot = 0;
+    if (d < 256) {
+        uint32_t tot = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; w++) tot += cnt[w][d];
-    hist[(int64_t)d * T + blockIdx.x] = tot;
+        for (int w = 0; w < NW; w++) tot += cnt[w][d];
+        hist[(int64_t)d * T + blockIdx.x] = tot;
+    }
 }
 
 template <typename K>
-__global__ __launch_bounds__(kThreads) void rs_scatter_k(const K *__restrict__ kin, const float *__restrict__ vin,
+__global__ __launch_bounds__(SortCfg<K>::kThreads) void rs_scatter_k(const K *__restrict__ kin, const float *__restrict__ vin,
                                                          K *__restrict__ kout, float *__restrict__ vout, int64_t n,
                                                          int shift, const uint64_t *__restrict__ offs, int64_t T) {
     constexpr int I = SortCfg<K>::kItems;
-    constexpr int TILE = SortCfg<K>::kTile;
-    __shared__ uint32_t cnt[kWaves][256];
+    constexpr int TILE = SortCfg<K>::kTile, NT = SortCfg<K>::kThreads, NW = SortCfg<K>::kWaves;
+    __shared__ uint32_t cnt[NW][256];
     __shared__ uint32_t tstart[256];
+    __shared__ uint32_t dtot[256];
     __shared__ uint64_t gbase[256];
-    __shared__ uint32_t lds_scan[kWaves];
     __shared__ K skeys[TILE];
     __shared__ float svals[TILE];
 
-    for (int q = threadIdx.x; q < kWaves * 256; q += kThreads) (&cnt[0][0])[q] = 0;
+    for (int q = threadIdx.x; q < NW * 256; q += NT) (&cnt[0][0])[q] = 0;
     __syncthreads();
     const int lane = __lane_id(), wave = threadIdx.x / 64;
     const int64_t base = (int64_t)blockIdx.x * TILE + (int64_t)wave * 64 * I;
@@ -233,20 +262,20 @@ __global__ __launch_bounds__(kThreads) void rs_scatter_k(const K *__restrict__ k
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    {
+    if (threadIdx.x < 256) {
         const int d = threadIdx.x;
-        uint32_t c[kWaves], run = 0;
+        uint32_t run = 0;
 #pragma unroll
-        for (int w = 0; w < kWaves; w++) c[w] = cnt[w][d];
-#pragma unroll
-        for (int w = 0; w < kWaves; w++) {
+        for (int w = 0; w < NW; w++) {
+            const uint32_t c = cnt[w][d];
             cnt[w][d] = run;
-            run += c[w];
+            run += c;
         }
-        uint32_t tot;
-        tstart[d] = block_exclusive_scan(run, &tot, lds_scan);
+        dtot[d] = run;
         gbase[d] = offs[(int64_t)d * T + blockIdx.x];
     }
+    __syncthreads();
+    if (wave == 0) wave_exclusive_scan256(dtot, tstart, lane);
     __syncthreads();
     for (int j = 0; j < I; j++) {
         if (dg[j] == 0xffffffffu) continue;
@@ -256,7 +285,7 @@ __global__ __launch_bounds__(kThreads) void rs_scatter_k(const K *__restrict__ k
     }
     __syncthreads();
     const int64_t nvalid = min((int64_t)TILE, n - (int64_t)blockIdx.x * TILE);
-    for (int i = threadIdx.x; i < nvalid; i += kThreads) {
+    for (int i = threadIdx.x; i < nvalid; i += NT) {
         const K key = skeys[i];
         const uint32_t d = KeyOps<K>::digit(key, shift);
         const uint64_t dst = gbase[d] + (uint64_t)(i - (int)tstart[d]);
@@ -279,10 +308,10 @@ int radix_sort_t(int nbits, int64_t n, K *keys, float *vals, K *keys_alt, float 
     float *src_v = vals, *dst_v = vals_alt;
     for (int p = 0; p < passes; p++) {
         const int shift = 8 * p;
-        rs_hist_k<K><<<(unsigned)T, kThreads, 0, s>>>(src_k, n, shift, hist, T);
+        rs_hist_k<K><<<(unsigned)T, SortCfg<K>::kThreads, 0, s>>>(src_k, n, shift, hist, T);
         int rc = device_scan<uint32_t, uint64_t, false>(hist, offs, 256 * T, nullptr, scan_ws, s);
         if (rc) return rc;
-        rs_scatter_k<K><<<(unsigned)T, kThreads, 0, s>>>(src_k, src_v, dst_k, dst_v, n, shift, offs, T);
+        rs_scatter_k<K><<<(unsigned)T, SortCfg<K>::kThreads, 0, s>>>(src_k, src_v, dst_k, dst_v, n, shift, offs, T);
         ALTO_HIP(hipGetLastError());
         std::swap(src_k, dst_k);
         std::swap(src_v, dst_v);
@@ -427,26 +456,6 @@ constexpr size_t seg_order_lds() {
     return (size_t)kSoTile * (sizeof(uint32_t) + sizeof(K) + sizeof(float));
 }
 
-__device__ __forceinline__ uint32_t wave_exclusive_scan256(const uint32_t *in, uint32_t *out, int lane) {
-    uint32_t v[4], sum = 0;
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-        v[q] = in[lane * 4 + q];
-        sum += v[q];
-    }
-    uint32_t inc = sum;
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = (uint32_t)__shfl_up((int)inc, off);
-        if (lane >= off) inc += y;
-    }
-    uint32_t run = inc - sum;
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-        out[lane * 4 + q] = run;
-        run += v[q];
-    }
-    return run;
-}
 
 // Buffers: rows R[2][n]; index and values alternate between the output
 // (okeys, ovals) and one scratch pair (ks, vs), chosen so that the last pass
