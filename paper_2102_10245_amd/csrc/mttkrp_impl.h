@@ -8,21 +8,25 @@
 // 16-byte load per lane.  Waves run independently (no workgroup barrier in
 // the main loop).  Per tile of G nonzeros per group:
 //   - every lane loads one nonzero of its own group (coalesced, prefetched one
-//     tile ahead) and de-linearizes it (bit-level scatter of the index);
+//     tile ahead) and de-linearizes it (bit-level scatter of the index): for
+//     indices of at most 64 bits, one LDS byte-table entry per index byte,
+//     OR-ed into a compact word holding all coordinates;
 //   - the group then walks its G nonzeros in order: coordinates and value come
-//     from the owning lane by cross-lane shuffle, the N-1 factor rows are
-//     gathered and multiplied, and the product is added to a register
-//     accumulator while the output row repeats; when the row changes the
-//     accumulator is flushed.
+//     from the owning lane by ds_swizzle, the N-1 factor rows are gathered
+//     (from LDS for small factor matrices staged there by the workgroup, else
+//     from memory at a 32-bit offset off a scalar base) and multiplied, and
+//     the product is added to a register accumulator while the output row
+//     repeats; when the row changes the accumulator is flushed.
 // A flush goes either to Temp (Algorithm 2, local staging: LDS rows
 // [T^s, T^e] of the segment's mode interval, merged into the output when the
 // segment is done: plain stores for rows no other segment covers, FP32 atomics
 // otherwise) or out with FP32 atomics (Algorithm 2, atomic update).  Atomic
 // flushes are queued in LDS and drained by the whole wave with R consecutive
 // lanes per output row, so each atomic instruction covers whole 128-byte
-// lines (on this GPU global atomics cost per line touched).  They can target
-// a per-XCD replica of the output (chosen by the XCC id register) so that the
-// lines a replica owns are only ever touched by one L2; a reduction adds the
+// lines (on this GPU global atomics cost per line touched); queue entries of
+// one row at consecutive slots are summed first.  They can target a per-XCD
+// replica of the output (chosen by the XCC id register) so that the lines a
+// replica owns are only ever touched by one L2; a reduction adds the
 // replicas into the output afterwards.  The atomics are device-scope either
 // way, so the result does not depend on which XCD a workgroup runs on.
 #pragma once
