@@ -247,13 +247,14 @@ __global__ __launch_bounds__(1024) void normal_eq_gj_k(const double *__restrict_
     for (int attempt = 0; attempt < 2; attempt++) {
         if (threadIdx.x == 0) {
             double tr = 0.0;
-            for (int r = 0; r < R; r++) {
-                double v = 1.0;
-                for (int m = 0; m < N; m++)
-                    if (m != skip) v *= G[(int64_t)m * RR + r * R + r];
-                tr += v;
-            }
-            ridge = attempt == 0 ? 0.0 : 1e-10 * tr / R;
+            if (attempt > 0)  // the trace is only needed for the retry
+                for (int r = 0; r < R; r++) {
+                    double v = 1.0;
+                    for (int m = 0; m < N; m++)
+                        if (m != skip) v *= G[(int64_t)m * RR + r * R + r];
+                    tr += v;
+                }
+            ridge = 1e-10 * tr / R;
         }
         __syncthreads();
         for (int e = threadIdx.x; e < RR; e += nt) {
@@ -270,16 +271,17 @@ __global__ __launch_bounds__(1024) void normal_eq_gj_k(const double *__restrict_
                 bad = true;
                 break;
             }
+            const double rp = 1.0 / piv;
             for (int i = threadIdx.x; i < R; i += nt) {
                 colk[i] = A[i * R + k];
-                rowk[i] = A[k * R + i] / piv;
+                rowk[i] = A[k * R + i] * rp;
             }
             __syncthreads();
             for (int e = threadIdx.x; e < RR; e += nt) {
                 const int i = e / R, j = e - i * R;
                 double v;
-                if (i == k) v = j == k ? 1.0 / piv : rowk[j];
-                else if (j == k) v = -colk[i] / piv;
+                if (i == k) v = j == k ? rp : rowk[j];
+                else if (j == k) v = -colk[i] * rp;
                 else v = A[e] - colk[i] * rowk[j];
                 A[e] = v;
             }
