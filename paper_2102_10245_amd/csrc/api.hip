@@ -117,14 +117,32 @@ int build_mode_order(alto_tensor *t, int mode, hipStream_t s) {
     Partition &P = *t->part;
     if (P.okeys[mode]) return ALTO_OK;
     const int64_t n = t->nnz;
-    if ((uint64_t)n > 0xffffffffull) return set_error(ALTO_E_INVAL, "segment-local orders need fewer than 2^32 nonzeros");
+    if ((uint64_t)(n + P.L - 1) / (uint64_t)std::max(1, P.L) > 0xffffffffull)
+        return set_error(ALTO_E_INVAL, "segment-local orders need segments of fewer than 2^32 nonzeros");
     const size_t kb = (size_t)t->key_bits / 8;
     int rc = ensure_workspace(t, seg_order_scratch(t->key_bits, n));
     if (rc) return rc;
-    ALTO_HIP(hipMalloc(&P.okeys[mode], kb * n));
-    ALTO_HIP(hipMalloc(&P.ovals[mode], sizeof(float) * n));
-    return launch_seg_order(t->key_bits, t->keys, t->vals, P.d_seg, P.L, t->tab, t->ctab, mode, t->nbits[mode],
-                            t->ws, n, P.okeys[mode], P.ovals[mode], s);
+    // the order is recorded only once it has been launched, so a failure
+    // leaves no half-built order behind
+    void *ok = nullptr;
+    float *ov = nullptr;
+    hipError_t e = hipMalloc(&ok, kb * n);
+    if (e == hipSuccess) e = hipMalloc(&ov, sizeof(float) * n);
+    if (e != hipSuccess) {
+        (void)hipFree(ok);
+        return hip_error(e, "hipMalloc(segment-local order)");
+    }
+    rc = launch_seg_order(t->key_bits, t->keys, t->vals, P.d_seg, P.L, t->tab, t->ctab, mode, t->nbits[mode], t->ws,
+                          n, ok, ov, s);
+    if (rc) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(ok);
+        (void)hipFree(ov);
+        return rc;
+    }
+    P.okeys[mode] = ok;
+    P.ovals[mode] = ov;
+    return ALTO_OK;
 }
 
 int cu_count() {
