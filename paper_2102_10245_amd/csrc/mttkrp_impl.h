@@ -139,7 +139,9 @@ struct MtCfg {
     static constexpr int kGPW = 64 / kG;                      // lane groups per wave
     static constexpr int kCols = RT ? 1 : 4;                  // column chunks per lane (generic rank)
     static constexpr int kNMax = NT ? NT : kMaxModes;
-    static constexpr int kU = kG >= 4 ? 4 : kG;               // nonzeros in flight per group
+    // nonzeros in flight per group (one for the generic-order kernels, which
+    // already gather up to seven rows per nonzero)
+    static constexpr int kU = NT == 0 ? 1 : (kG >= 4 ? 4 : kG);
     // flush queue (rank-specialized atomic path): rows per wave
     static constexpr bool kQueue = RT != 0 && RT <= 64;
     static constexpr int kQRows = kQueue ? 2 * kGPW : 0;      // drained once it holds more than one row per group
@@ -467,8 +469,14 @@ int launch_mt_cfg(const MtLaunch &a, hipStream_t s) {
     if (tab_bytes && !a.ctab) return set_error(ALTO_E_INVAL, "internal: missing byte tables");
     const int per = (a.n_list + 7) / 8;
     const unsigned grid = (unsigned)per * 8;
-    auto kern = a.staged ? (a.wide ? mttkrp_k<K, NT, RT, FT, true, true> : mttkrp_k<K, NT, RT, FT, true, false>)
-                         : (a.wide ? mttkrp_k<K, NT, RT, FT, false, true> : mttkrp_k<K, NT, RT, FT, false, false>);
+    // generic-order and generic-rank kernels always use 64-bit factor offsets
+    decltype(&mttkrp_k<K, NT, RT, FT, true, true>) kern;
+    if constexpr (NT == 0 || RT == 0) {
+        kern = a.staged ? mttkrp_k<K, NT, RT, FT, true, true> : mttkrp_k<K, NT, RT, FT, false, true>;
+    } else {
+        kern = a.staged ? (a.wide ? mttkrp_k<K, NT, RT, FT, true, true> : mttkrp_k<K, NT, RT, FT, true, false>)
+                        : (a.wide ? mttkrp_k<K, NT, RT, FT, false, true> : mttkrp_k<K, NT, RT, FT, false, false>);
+    }
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute(MaxDynamicSharedMemorySize)");
