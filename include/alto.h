@@ -55,7 +55,7 @@ typedef enum {
 
 /* Conflict resolution for the MTTKRP output (Section 3.3, Algorithm 2). */
 typedef enum {
-    ALTO_STRATEGY_AUTO = 0,    /* selector network if loaded, else the reuse rule of Section 3.3 */
+    ALTO_STRATEGY_AUTO = 0,    /* the plan alto_select describes (network, timing fallback, reuse rule) */
     ALTO_STRATEGY_ATOMIC = 1,  /* every partial result goes to the output with FP32 atomics */
     ALTO_STRATEGY_STAGED = 2,  /* per-segment partials in on-chip local memory over the segment's
                                   mode interval, then merged into the output; segments whose
@@ -183,10 +183,17 @@ int cp_als(alto_tensor *t, int R, int iters, int prec, void *const *factors, dou
 
 /*
  * alto_select — the execution the library would pick for an MTTKRP of this
- * mode and rank: the selector network's choice when weights are loaded and
- * the tensor lies inside the range it was trained on, else the reuse rule
- * of Section 3.3 (staged if nnz / I_mode > 4, atomic otherwise) with the
- * current L.  Host only.
+ * mode and rank (ALTO_STRATEGY_AUTO):
+ *   - no selector weights loaded: the reuse rule of Section 3.3 (staged if
+ *     nnz / I_mode > 4, atomic otherwise) with the current L;
+ *   - weights loaded, tensor inside the range the network was trained on:
+ *     the network's choice;
+ *   - weights loaded, tensor outside that range: the fastest candidate found
+ *     by timing every (strategy, L) the network chooses among.  An AUTO
+ *     alto_mttkrp or cp_als does that timing on first use of (mode, R, prec)
+ *     and the tensor keeps the result; until then this call reports the reuse
+ *     rule.
+ * Host only.
  */
 int alto_select(const alto_tensor *t, int mode, int R, int prec, alto_exec *out);
 

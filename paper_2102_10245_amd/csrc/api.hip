@@ -301,7 +301,44 @@ int ensure_workspace(alto_tensor *t, size_t bytes) {
     return ALTO_OK;
 }
 
-int resolve_strategy(const alto_tensor *t, int mode, int R, int prec, const alto_exec *ex, alto_exec *res) {
+// Exhaustive timing: run every candidate (strategy, L) once to build its
+// plan and order, time a second run with events on the stream, keep the
+// fastest.  The selector's fallback outside its training range.
+int autotune(alto_tensor *t, const void *const *factors, int R, int prec, int mode, float *out, hipStream_t s,
+             alto_exec *best) {
+    const std::vector<alto_exec> cands = selector_candidates();
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ALTO_HIP(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_error(he, "hipEventCreate");
+    }
+    float best_ms = INFINITY;
+    int rc = ALTO_OK;
+    for (const alto_exec &c : cands) {
+        rc = plan_and_run_mttkrp(t, factors, R, prec, mode, out, &c, s);
+        if (rc) break;
+        he = hipEventRecord(e0, s);
+        if (he == hipSuccess) rc = plan_and_run_mttkrp(t, factors, R, prec, mode, out, &c, s);
+        if (he == hipSuccess && !rc) he = hipEventRecord(e1, s);
+        if (he == hipSuccess && !rc) he = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (he == hipSuccess && !rc) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess) rc = hip_error(he, "timing a candidate plan");
+        if (rc) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            *best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+int resolve_strategy(alto_tensor *t, const void *const *factors, int R, int prec, int mode, float *out,
+                     const alto_exec *ex, hipStream_t s, alto_exec *res) {
     if (ex && (ex->strategy < 0 || ex->strategy > 3)) return set_error(ALTO_E_INVAL, "unknown strategy");
     if (ex && ex->num_segments < 0) return set_error(ALTO_E_INVAL, "num_segments must be >= 0");
     if (ex && ex->strategy != ALTO_STRATEGY_AUTO) {
@@ -309,9 +346,20 @@ int resolve_strategy(const alto_tensor *t, int mode, int R, int prec, const alto
         return ALTO_OK;
     }
     alto_exec sel;
-    const int rc = alto_select(t, mode, R, prec, &sel);
-    if (rc) return rc;
-    if (ex && ex->num_segments > 0) sel.num_segments = ex->num_segments;
+    const int src = select_plan(t, mode, R, prec, &sel);
+    if (ex && ex->num_segments > 0) {
+        sel.num_segments = ex->num_segments;  // a fixed L: the strategy as chosen
+    } else if (src == kPlanOutside && t->nnz > 0) {
+        const uint64_t key = tuned_key(mode, R, prec);
+        auto it = t->tuned.find(key);
+        if (it == t->tuned.end()) {
+            alto_exec best{};
+            const int rc = autotune(t, factors, R, prec, mode, out, s, &best);
+            if (rc) return rc;
+            it = t->tuned.emplace(key, best).first;
+        }
+        sel = it->second;
+    }
     *res = sel;
     return ALTO_OK;
 }
@@ -331,7 +379,7 @@ int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int p
         if (m != mode && ((uintptr_t)factors[m] & 15u)) return set_error(ALTO_E_INVAL, "factor pointer not 16-byte aligned");
     if ((uintptr_t)out & 15u) return set_error(ALTO_E_INVAL, "output pointer not 16-byte aligned");
     alto_exec plan;
-    rc = resolve_strategy(t, mode, R, prec, ex, &plan);
+    rc = resolve_strategy(t, factors, R, prec, mode, out, ex, s, &plan);
     if (rc) return rc;
     if (plan.num_segments > 0) {
         rc = select_partition(t, plan.num_segments, s);

@@ -186,6 +186,9 @@ struct alto_tensor {
     // per-XCD output replicas for atomic updates (grown on demand)
     float *rep = nullptr;
     size_t rep_bytes = 0;
+    // plans found by timing every candidate, for (mode, R, prec) outside the
+    // selector's training range (see tuned_key)
+    std::map<uint64_t, alto_exec> tuned;
 };
 
 namespace alto {
@@ -236,6 +239,16 @@ int mlp_backward(int B, int F, int H, int K, const float *params, const float *x
                  const float *mask, float *grads, float *loss, hipStream_t s);
 int mlp_adam(int64_t P, float *params, const float *grads, float *m, float *v, float lr, float b1, float b2,
              float eps, int t, hipStream_t s);
+
+// selector.hip: where an automatic plan comes from
+enum { kPlanRule = 0, kPlanNet = 1, kPlanOutside = 2 };
+// the selector's (or, without weights, the reuse rule's) plan and its source
+int select_plan(const alto_tensor *t, int mode, int R, int prec, alto_exec *out);
+// every (strategy, L) the selector chooses among
+std::vector<alto_exec> selector_candidates();
+inline uint64_t tuned_key(int mode, int R, int prec) {
+    return (uint64_t)mode | ((uint64_t)R << 8) | ((uint64_t)prec << 20);
+}
 
 // api.hip: execution planning shared with cp_als
 int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int prec, int mode, float *out,

@@ -51,13 +51,76 @@ void features(const alto_tensor *t, int mode, int R, int prec, float *f) {
     f[11] = (float)std::log2(I * R);
 }
 
+const int kOrder[3] = {ALTO_STRATEGY_ATOMIC, ALTO_STRATEGY_STAGED, ALTO_STRATEGY_SORTED};
+
 void heuristic(const alto_tensor *t, int mode, alto_exec *out) {
     const double reuse = (double)t->nnz / (double)t->dims[mode];
     out->strategy = reuse > 4.0 ? ALTO_STRATEGY_STAGED : ALTO_STRATEGY_ATOMIC;
     out->num_segments = 0;
 }
 
+// The plan of (tensor, mode, R, prec) and where it came from.
+int select_impl(const alto_tensor *t, int mode, int R, int prec, alto_exec *out) {
+    std::lock_guard<std::mutex> lk(g_sel_mu);
+    if (!g_sel.loaded || t->nnz == 0) {
+        heuristic(t, mode, out);
+        return kPlanRule;
+    }
+    const Selector &s = g_sel;
+    float f[kF];
+    features(t, mode, R, prec, f);
+    for (int q = 0; q < kF; q++) {
+        const float span = s.fmax[q] - s.fmin[q];
+        const float tol = 0.25f * span + 0.5f;
+        if (f[q] < s.fmin[q] - tol || f[q] > s.fmax[q] + tol) {
+            heuristic(t, mode, out);
+            return kPlanOutside;
+        }
+    }
+    std::vector<float> h1(s.H), h2(s.H);
+    for (int j = 0; j < s.H; j++) {
+        float a = s.b1[j];
+        for (int q = 0; q < s.F; q++) a += s.W1[(size_t)j * s.F + q] * ((f[q] - s.mean[q]) / s.scale[q]);
+        h1[j] = a > 0.f ? a : 0.f;
+    }
+    for (int j = 0; j < s.H; j++) {
+        float a = s.b2[j];
+        for (int q = 0; q < s.H; q++) a += s.W2[(size_t)j * s.H + q] * h1[q];
+        h2[j] = a > 0.f ? a : 0.f;
+    }
+    int best = 0;
+    float best_y = INFINITY;
+    for (int k = 0; k < s.K; k++) {
+        float a = s.b3[k];
+        for (int q = 0; q < s.H; q++) a += s.W3[(size_t)k * s.H + q] * h2[q];
+        if (a < best_y) {
+            best_y = a;
+            best = k;
+        }
+    }
+    out->strategy = kOrder[best / s.nL];
+    out->num_segments = (int)s.Ls[best % s.nL];
+    return kPlanNet;
+}
+
 }  // namespace
+
+int select_plan(const alto_tensor *t, int mode, int R, int prec, alto_exec *out) {
+    return select_impl(t, mode, R, prec, out);
+}
+
+std::vector<alto_exec> selector_candidates() {
+    std::lock_guard<std::mutex> lk(g_sel_mu);
+    std::vector<alto_exec> c;
+    const int nL = g_sel.loaded ? g_sel.nL : 5;
+    const int S = g_sel.loaded ? g_sel.K / g_sel.nL : 3;
+    static const int kDefaultLs[5] = {512, 1024, 2048, 4096, 8192};
+    for (int st = 0; st < S; st++)
+        for (int q = 0; q < nL; q++)
+            c.push_back(alto_exec{kOrder[st], g_sel.loaded ? (int)g_sel.Ls[q] : kDefaultLs[q]});
+    return c;
+}
+
 }  // namespace alto
 
 using namespace alto;
@@ -116,46 +179,11 @@ int alto_select(const alto_tensor *t, int mode, int R, int prec, alto_exec *out)
     if (!t || !out) return set_error(ALTO_E_INVAL, "null argument");
     if (mode < 0 || mode >= t->N) return set_error(ALTO_E_INVAL, "mode out of range");
     if (R < 1 || R > ALTO_MAX_RANK) return set_error(ALTO_E_INVAL, "R must be in 1..256");
-    std::lock_guard<std::mutex> lk(g_sel_mu);
-    if (!g_sel.loaded || t->nnz == 0) {
-        heuristic(t, mode, out);
-        return ALTO_OK;
+    if (select_impl(t, mode, R, prec, out) == kPlanOutside) {
+        // outside the training range: the plan found by timing, once there is one
+        const auto it = t->tuned.find(tuned_key(mode, R, prec));
+        if (it != t->tuned.end()) *out = it->second;
     }
-    const Selector &s = g_sel;
-    float f[kF];
-    features(t, mode, R, prec, f);
-    for (int q = 0; q < kF; q++) {
-        const float span = s.fmax[q] - s.fmin[q];
-        const float tol = 0.25f * span + 0.5f;
-        if (f[q] < s.fmin[q] - tol || f[q] > s.fmax[q] + tol) {
-            heuristic(t, mode, out);
-            return ALTO_OK;
-        }
-    }
-    std::vector<float> h1(s.H), h2(s.H);
-    for (int j = 0; j < s.H; j++) {
-        float a = s.b1[j];
-        for (int q = 0; q < s.F; q++) a += s.W1[(size_t)j * s.F + q] * ((f[q] - s.mean[q]) / s.scale[q]);
-        h1[j] = a > 0.f ? a : 0.f;
-    }
-    for (int j = 0; j < s.H; j++) {
-        float a = s.b2[j];
-        for (int q = 0; q < s.H; q++) a += s.W2[(size_t)j * s.H + q] * h1[q];
-        h2[j] = a > 0.f ? a : 0.f;
-    }
-    int best = 0;
-    float best_y = INFINITY;
-    for (int k = 0; k < s.K; k++) {
-        float a = s.b3[k];
-        for (int q = 0; q < s.H; q++) a += s.W3[(size_t)k * s.H + q] * h2[q];
-        if (a < best_y) {
-            best_y = a;
-            best = k;
-        }
-    }
-    static const int order[3] = {ALTO_STRATEGY_ATOMIC, ALTO_STRATEGY_STAGED, ALTO_STRATEGY_SORTED};
-    out->strategy = order[best / s.nL];
-    out->num_segments = (int)s.Ls[best % s.nL];
     return ALTO_OK;
 }
 

@@ -152,3 +152,39 @@ def test_library_selection_and_live_gain():
     finally:
         alto.selector_load(None)
         t.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.skipif(not _gpu(), reason="needs a GPU")
+def test_outside_training_range_times_every_candidate():
+    """A tensor outside the network's training range (far fewer nonzeros than
+    any corpus tensor): alto_select reports the reuse rule until an AUTO
+    MTTKRP has timed every candidate; afterwards it reports the kept plan,
+    which is one of the candidates, and the AUTO result matches the oracle."""
+    import torch
+    import synth
+    from gpu_common import rel_fro
+    rec = synth.Recipe("tiny_outside", (300, 200, 100), 20_000, (0.8, 0, 0), seed=31)
+    coords, vals = synth.coo(rec)
+    c = torch.from_numpy(coords.view(np.int32)).cuda()
+    v = torch.from_numpy(vals).cuda()
+    t = alto.AltoTensor.build(c, v, rec.dims)
+    R = 16
+    try:
+        assert alto.load_default_selector()
+        cands = {st.candidate(k) for k in range(st.K)}
+        fs = synth.factors(rec.seed + 1, rec.dims, R)
+        fd = [torch.from_numpy(f).cuda() for f in fs]
+        for mode in range(3):
+            reuse = t.info()["fiber_reuse"][mode]
+            before = t.select(mode, R, "f32")
+            assert before[0] == ("staged" if reuse > 4 else "atomic")
+            out = t.mttkrp(fd, mode, strategy="auto").cpu().numpy()
+            after = t.select(mode, R, "f32")
+            assert after in cands, after
+            assert t.select(mode, R, "f32") == after  # kept, not timed again
+            ref = oracle.mttkrp(rec.dims, coords, vals, fs, mode)
+            assert rel_fro(out, ref) <= 1e-5
+    finally:
+        alto.selector_load(None)
+        t.close()
