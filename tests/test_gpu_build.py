@@ -161,3 +161,37 @@ def test_mode_order_bit_exact(rec, kb, L):
         else:
             assert np.allclose(gv, ov[perm], rtol=2e-6, atol=0), n
     t.close()
+
+
+def test_largest_dimension_bit_exact():
+    # a mode of 2^32 rows (32 index bits, a full-width coordinate field in the
+    # compact form), with both extreme coordinates present
+    dims = (2 ** 32, 5, 3)
+    rng = np.random.default_rng(41)
+    M = 60_000
+    coords = np.stack([rng.integers(0, 2 ** 32, M, dtype=np.uint64).astype(np.uint32),
+                       rng.integers(0, 5, M).astype(np.uint32), rng.integers(0, 3, M).astype(np.uint32)])
+    coords[:, 0] = (0, 0, 0)
+    coords[:, 1] = (2 ** 32 - 1, 4, 2)
+    vals = rng.random(M).astype(np.float32)
+    c, v = to_dev(coords, vals)
+    L = 16
+    t = alto.AltoTensor.build(c, v, dims, num_segments=L)
+    info = t.info()
+    (olo, ohi), ov, lay, _ = oracle_alto(dims, coords, vals)
+    assert info["index_bits"] == lay.B == 37 and info["key_bits"] == 64
+    keys, _ = t.export_keys()
+    glo, ghi = keys_numpy(keys, info["key_bits"])
+    assert np.array_equal(glo, olo) and np.array_equal(ghi, ohi)
+    oseg = oracle.partition(len(olo), L)
+    seg, ivl = t.export_partition()
+    assert np.array_equal(seg.cpu().numpy(), oseg)
+    assert np.array_equal(ivl.cpu().numpy().view(np.uint32), oracle.intervals(lay, oseg, (olo, ohi)))
+    segid = np.repeat(np.arange(len(oseg) - 1), np.diff(oseg))
+    oc = oracle.decode(lay, (olo, ohi))
+    for n in range(3):
+        perm = np.lexsort((np.arange(len(olo)), oc[n], segid))
+        k, _ = t.export_mode_order(n)
+        klo, khi = keys_numpy(k, info["key_bits"])
+        assert np.array_equal(klo, olo[perm]) and np.array_equal(khi, ohi[perm]), n
+    t.close()
