@@ -491,31 +491,26 @@ __global__ __launch_bounds__(kSoThreads) void seg_order_k(const K *__restrict__ 
         }
         return;
     }
-    // pass p reads (R[p&1], D_p) and writes (R[(p+1)&1], D_{p+1}), D_passes = output
+    // pass p reads (R[p&1], D_p) and writes (R[(p+1)&1], D_{p+1}); D_0 is the
+    // tensor itself, D_passes the output, and D_p for 0 < p < passes the
+    // output or the scratch pair, alternating
     K *Dk[2] = {okeys, ks};
     float *Dv[2] = {ovals, vs};
-    // D_p is the output when passes - p is even
-    auto dk = [&](int p) { return Dk[(passes - p) & 1]; };
-    auto dv = [&](int p) { return Dv[(passes - p) & 1]; };
+    auto dk = [&](int p) -> K * { return Dk[(passes - p) & 1]; };
+    auto dv = [&](int p) -> float * { return Dv[(passes - p) & 1]; };
     uint32_t *Rr[2] = {R0, R1};
     // decode the rows into the pass-0 input; the histogram of the first digit on the way
     if (threadIdx.x < 256) hist[threadIdx.x] = 0;
     if constexpr (kTab > 0)
         for (int q = threadIdx.x; q < kTab; q += kSoThreads) ltab[q] = ctab[q];
     __syncthreads();
-    {
-        K *k0 = dk(0);
-        float *v0 = dv(0);
-        for (int64_t i = threadIdx.x; i < n; i += kSoThreads) {
-            const K key = keys[sb + i];
-            uint32_t row;
-            if constexpr (kTab > 0) row = (uint32_t)(compact_index(key, ltab) >> tab.coff[mode]) & tab.cmask[mode];
-            else row = extract_mode(key, tab, mode);
-            Rr[0][sb + i] = row;
-            k0[sb + i] = key;
-            v0[sb + i] = vals[sb + i];
-            atomicAdd(&hist[row & 255u], 1u);
-        }
+    for (int64_t i = threadIdx.x; i < n; i += kSoThreads) {
+        const K key = keys[sb + i];
+        uint32_t row;
+        if constexpr (kTab > 0) row = (uint32_t)(compact_index(key, ltab) >> tab.coff[mode]) & tab.cmask[mode];
+        else row = extract_mode(key, tab, mode);
+        Rr[0][sb + i] = row;
+        atomicAdd(&hist[row & 255u], 1u);
     }
     __syncthreads();
     const uint64_t lt = lanemask_lt();
@@ -524,8 +519,8 @@ __global__ __launch_bounds__(kSoThreads) void seg_order_k(const K *__restrict__ 
         const bool last = p == passes - 1;
         const uint32_t *srow = Rr[p & 1];
         uint32_t *drow = Rr[(p + 1) & 1];
-        const K *skey = dk(p);
-        const float *sval = dv(p);
+        const K *skey = p == 0 ? keys : dk(p);
+        const float *sval = p == 0 ? vals : dv(p);
         K *dkey = dk(p + 1);
         float *dval = dv(p + 1);
         // exclusive scan of this digit's histogram; the next digit's is
