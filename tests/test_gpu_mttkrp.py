@@ -143,3 +143,29 @@ def test_full_size_sampled_rows():
             for q, r in enumerate(rows):
                 assert rel_fro(out[r], ref[q]) <= TOL, (mode, prec, int(r), rel_fro(out[r], ref[q]))
     t.close()
+
+
+@pytest.mark.parametrize("name,nnz,R", [("zipf4_1Mx100kx10kx500_150M", 600_000, 32),
+                                        ("uniform3_1000x800x600_100k", 0, 16)])
+def test_bf16_factor_error_budget(name, nnz, R):
+    """Factors that are not exact in bfloat16 (Gaussian FP32): the BF16 path
+    (factors rounded to bfloat16, FP32 accumulation) stays within 1e-2
+    relative Frobenius error of the FP64 oracle on the FP32 factors, and the
+    FP32 path within 1e-5; the errors of every strategy are printed."""
+    torch = pytest.importorskip("torch")
+    rec = small(name, nnz) if nnz else synth.WORKLOADS[name]
+    coords, vals = synth.coo(rec)
+    c, v = to_dev(coords, vals)
+    t = alto.AltoTensor.build(c, v, rec.dims)
+    rng = np.random.default_rng(rec.seed + 99)
+    fs = [rng.standard_normal((d, R)).astype(np.float32) for d in rec.dims]
+    f32 = factors_dev(fs, "f32")
+    bf16 = [f.to(torch.bfloat16) for f in f32]
+    for mode in range(len(rec.dims)):
+        ref = oracle.mttkrp(rec.dims, coords, vals, fs, mode)
+        for st in ("atomic", "staged", "sorted"):
+            e32 = rel_fro(t.mttkrp(f32, mode, strategy=st).cpu().numpy(), ref)
+            e16 = rel_fro(t.mttkrp(bf16, mode, strategy=st).cpu().numpy(), ref)
+            print(f"error {rec.name} mode {mode} {st}: fp32 {e32:.2e} bf16 {e16:.2e}", flush=True)
+            assert e32 <= TOL and e16 <= 1e-2, (mode, st, e32, e16)
+    t.close()
