@@ -91,6 +91,26 @@ int make_layout(alto_tensor *t, int key_bits_req) {
         coff += t->nbits[n];
     }
     t->h_ctab.clear();
+    t->tab.tbytes128 = 0;
+    if (t->key_bits == 128) {
+        // 128-bit compact word {lo, hi}; a coordinate may straddle the halves
+        int cmap[128];
+        for (int p = 0; p < 128; p++) cmap[p] = -1;
+        for (int n = 0; n < N; n++)
+            for (int k = 0; k < t->nbits[n]; k++) cmap[where[n][k]] = (int)t->tab.coff[n] + k;
+        const int nb = std::max(1, (pos + 7) / 8);
+        t->tab.tbytes128 = nb;
+        t->h_ctab.assign((size_t)nb * 256 * 16, 0);
+        for (int j = 0; j < nb; j++)
+            for (int v = 0; v < 256; v++) {
+                uint64_t e[2] = {0, 0};
+                for (int b = 0; b < 8; b++) {
+                    const int c = cmap[8 * j + b];
+                    if (((v >> b) & 1) && c >= 0) e[c >> 6] |= 1ull << (c & 63);
+                }
+                std::memcpy(&t->h_ctab[((size_t)j * 256 + v) * 16], e, 16);  // {lo, hi}
+            }
+    }
     if (t->key_bits <= 64) {
         int cmap[64];
         for (int p = 0; p < 64; p++) cmap[p] = -1;
@@ -445,7 +465,15 @@ int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int p
     a.dec.smask = 0;
     const int64_t seg_len = t->nnz / std::max(1, t->part->L);
     if ((R == 8 || R == 16 || R == 32 || R == 64) && seg_len >= 65536) {
-        const uint64_t budget = (uint64_t)std::max<long>(0, env_long("ALTO_STAGE_FACTOR_BYTES", 64 * 1024));
+        // what a 1024-thread launch needs besides: the flush queues (two rows
+        // per lane group) and the byte tables
+        const int vec = prec == ALTO_PREC_BF16 ? 8 : 4, gpw = 64 / (R / vec);
+        const uint64_t queue = 16ull * 2 * gpw * (R + 1) * 4;
+        const uint64_t table = t->key_bits <= 64 ? (uint64_t)(t->key_bits / 8) * 256 * (t->key_bits / 8)
+                                                 : (uint64_t)t->tab.tbytes128 * 256 * 16;
+        const uint64_t room = 160 * 1024 - std::min<uint64_t>(160 * 1024, queue + table + 512);
+        const uint64_t budget =
+            std::min<uint64_t>(room, (uint64_t)std::max<long>(0, env_long("ALTO_STAGE_FACTOR_BYTES", 64 * 1024)));
         int js[kMaxModes];
         for (int j = 0; j < t->N - 1; j++) js[j] = j;
         std::sort(js, js + t->N - 1, [&](int x, int y) { return t->dims[a.dec.om[x]] < t->dims[a.dec.om[y]]; });

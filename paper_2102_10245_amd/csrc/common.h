@@ -67,6 +67,8 @@ struct KeyOps<u128> {
     }
     __device__ __forceinline__ static bool eq(const u128 &a, const u128 &b) { return a.lo == b.lo && a.hi == b.hi; }
     __device__ __forceinline__ static u128 zero() { return u128{0ull, 0ull}; }
+    __device__ __forceinline__ static uint64_t lo_word(const u128 &k) { return k.lo; }
+    __device__ __forceinline__ static uint64_t hi_word(const u128 &k) { return k.hi; }
 };
 
 // Bit runs of every mode: run r of mode n moves `len` consecutive bits from
@@ -75,10 +77,15 @@ struct RunTable {
     int N;
     int nruns[kMaxModes];
     uint32_t run[kMaxModes][kMaxRuns];
-    // Compact form (indices of at most 64 bits): mode n's coordinate is bits
-    // [coff[n], coff[n] + b_n) of the word that the byte tables assemble.
+    // Compact form: mode n's coordinate is bits [coff[n], coff[n] + b_n) of
+    // the word that the byte tables assemble (64 bits at most for indices of
+    // at most 64 bits; for 128-bit indices two 64-bit words, no coordinate
+    // straddling them, when the modes can be packed that way).
     uint32_t coff[kMaxModes];
     uint32_t cmask[kMaxModes];
+    // 128-bit indices: index bytes covered by the byte tables (0: no tables,
+    // the bit runs above de-linearize)
+    int tbytes128;
 };
 
 __device__ __forceinline__ int run_kpos(uint32_t r) { return (int)(r & 0xffu); }

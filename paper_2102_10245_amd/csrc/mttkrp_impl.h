@@ -139,9 +139,11 @@ struct MtCfg {
     static constexpr int kGPW = 64 / kG;                      // lane groups per wave
     static constexpr int kCols = RT ? 1 : 4;                  // column chunks per lane (generic rank)
     static constexpr int kNMax = NT ? NT : kMaxModes;
-    // nonzeros in flight per group (one for the generic-order kernels, which
-    // already gather up to seven rows per nonzero)
-    static constexpr int kU = NT == 0 ? 1 : (kG >= 4 ? 4 : kG);
+    // nonzeros in flight per group: four for orders 3 and 4, two for order 5
+    // (four gathered rows each; keeps the registers below the spill point),
+    // one for the generic-order kernels (up to seven rows each)
+    static constexpr int kUMax = NT == 0 ? 1 : (NT >= 5 ? 2 : 4);
+    static constexpr int kU = kG >= kUMax ? kUMax : kG;
     // flush queue (rank-specialized atomic path): rows per wave
     static constexpr bool kQueue = RT != 0 && RT <= 64;
     static constexpr int kQRows = kQueue ? 2 * kGPW : 0;      // drained once it holds more than one row per group
@@ -214,6 +216,12 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
         const uint4 *src = reinterpret_cast<const uint4 *>(ctab);
         uint4 *dst = reinterpret_cast<uint4 *>(ltab);
         for (int q = threadIdx.x; q < n16; q += blockDim.x) dst[q] = src[q];
+    } else {
+        // 128-bit indices: tbytes128 tables of 256 {lo, hi} entries
+        const int n16 = tab.tbytes128 * 256;
+        const uint4 *src = reinterpret_cast<const uint4 *>(ctab);
+        uint4 *dst = reinterpret_cast<uint4 *>(ltab);
+        for (int q = threadIdx.x; q < n16; q += blockDim.x) dst[q] = src[q];
     }
     if constexpr (RT != 0 && !kStaged) {
         // small factor matrices of other modes, staged whole
@@ -224,7 +232,7 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
             for (uint32_t q = threadIdx.x; q < dec.sbytes[j] / 16u; q += blockDim.x) dst[q] = src[q];
         }
     }
-    if (kStaged || kTab > 0 || dec.smask) __syncthreads();
+    __syncthreads();
 
     uint32_t cur = kNoRow;
     float acc[NCOL][VEC];
@@ -310,9 +318,28 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
             for (int j = 0; j < NO; j++) idx[j] = j < N - 1 ? (uint32_t)(cw >> dec.coff[j]) & dec.cmask[j] : 0u;
             myrow = (uint32_t)(cw >> dec.coff[N - 1]) & dec.cmask[N - 1];
         } else {
+            // 128-bit indices: OR of one {lo, hi} entry per index byte
+            uint64_t clo = 0, chi = 0;
+            const u128 *lt = reinterpret_cast<const u128 *>(ltab);
 #pragma unroll
-            for (int j = 0; j < NO; j++) idx[j] = (j < N - 1 && ok) ? extract_mode(key, tab, dec.om[j]) : 0u;
-            myrow = extract_mode(key, tab, mode);
+            for (int b = 0; b < 16; b++) {
+                if (b >= tab.tbytes128) break;
+                const uint64_t w = b < 8 ? KeyOps<K>::lo_word(key) : KeyOps<K>::hi_word(key);
+                const u128 e = lt[b * 256 + (int)((w >> (8 * (b & 7))) & 0xffu)];
+                clo |= e.lo;
+                chi |= e.hi;
+            }
+            // bits [off, off + 32) of the 128-bit word (a field may straddle the halves)
+            auto field = [&](uint32_t off, uint32_t mask) {
+                uint64_t w;
+                if (off >= 64) w = chi >> (off - 64);
+                else if (off == 0) w = clo;
+                else w = (clo >> off) | (chi << (64 - off));
+                return (uint32_t)w & mask;
+            };
+#pragma unroll
+            for (int j = 0; j < NO; j++) idx[j] = j < N - 1 ? field(dec.coff[j], dec.cmask[j]) : 0u;
+            myrow = field(dec.coff[N - 1], dec.cmask[N - 1]);
         }
         if (!ok) myrow = kNoRow;
 
@@ -455,7 +482,8 @@ int launch_mt_cfg(const MtLaunch &a, hipStream_t s) {
     const size_t main_lds = a.staged ? (size_t)a.temp_rows * temp_stride(a.R) * 4
                                      : (size_t)mt_queue_bytes<NT, RT, FT>(a.threads);
     const size_t tab_off = (main_lds + 15) / 16 * 16;
-    const size_t tab_bytes = (size_t)byte_table_entries(8 * (int)sizeof(K)) * sizeof(K);
+    const size_t tab_bytes = sizeof(K) <= 8 ? (size_t)byte_table_entries(8 * (int)sizeof(K)) * sizeof(K)
+                                            : (size_t)a.tab.tbytes128 * 256 * 16;
     size_t lds = tab_off + tab_bytes;
     ModeDec dec = a.dec;
     if (RT == 0 || a.staged) dec.smask = 0;
