@@ -8,9 +8,9 @@
 // 16-byte load per lane.  Waves run independently (no workgroup barrier in
 // the main loop).  Per tile of G nonzeros per group:
 //   - every lane loads one nonzero of its own group (coalesced, prefetched one
-//     tile ahead) and de-linearizes it (bit-level scatter of the index): for
-//     indices of at most 64 bits, one LDS byte-table entry per index byte,
-//     OR-ed into a compact word holding all coordinates;
+//     tile ahead) and de-linearizes it (bit-level scatter of the index): one
+//     LDS byte-table entry per index byte, OR-ed into a compact word holding
+//     all coordinates (a {lo, hi} pair of words for 128-bit indices);
 //   - the group then walks its G nonzeros in order: coordinates and value come
 //     from the owning lane by ds_swizzle, the N-1 factor rows are gathered
 //     (from LDS for small factor matrices staged there by the workgroup, else
