@@ -223,8 +223,8 @@ __global__ __launch_bounds__(kT) void fit_k(const double *__restrict__ G, int N,
 // for the column norms, and a pass that solves again, scales by lambda,
 // stores the factor and accumulates its Gram matrix (and, for the last mode,
 // the inner product of the fit) from the stored values.  Rows are processed
-// in tiles of 1024 / R rows staged in LDS; thread (row group, column c) keeps
-// column c of V^-1 in registers.
+// in tiles of 1024 / R rows staged in LDS, several tiles' loads in flight;
+// thread (row group, column c) keeps column c of V^-1 in registers.
 
 // V = Hadamard of the Grams of every mode except `skip` (+ ridge on the
 // diagonal), inverted in place by Gauss-Jordan elimination without pivoting.
@@ -303,17 +303,45 @@ struct SolveShape {
     static constexpr int kRG = kT / R;       // row groups (threads per column)
     static constexpr int kRPT = 4;           // rows per thread per tile
     static constexpr int kTR = kRG * kRPT;   // rows per tile
+    static constexpr int kDepth = 4;         // tiles in flight per block (loads issued ahead)
 };
 
-// Stage rows [r0, r0 + TR) of Mn in LDS (zeros past I), one float4 per thread.
+// Thread's float4 of tile `tile` of Mn (zeros past I, no load at all there).
 template <int R>
-__device__ __forceinline__ void stage_rows(const float *__restrict__ Mn, uint64_t I, uint64_t r0, float *Ms) {
+__device__ __forceinline__ float4 load_tile(const float *__restrict__ Mn, uint64_t I, uint64_t tile) {
     constexpr int TR = SolveShape<R>::kTR;
     static_assert(TR * R == 4 * kT, "a tile is one float4 per thread");
-    const uint64_t e0 = r0 * R + 4u * threadIdx.x;
+    const uint64_t r0 = tile * TR;
     float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (r0 + (4u * threadIdx.x) / R < I) q = *reinterpret_cast<const float4 *>(Mn + e0);
-    reinterpret_cast<float4 *>(Ms)[threadIdx.x] = q;
+    if (r0 + (4u * threadIdx.x) / R < I) q = *reinterpret_cast<const float4 *>(Mn + r0 * R + 4u * threadIdx.x);
+    return q;
+}
+
+// Runs body(tile) for the block's tiles (blockIdx.x, + gridDim.x, ...) with
+// the tile staged in Ms.  The loads of the next kDepth tiles are in flight
+// while a tile is processed, so a block keeps kDepth * 4 KiB of reads
+// outstanding instead of stalling on one tile at a time.
+template <int R, class Body>
+__device__ __forceinline__ void for_each_tile(const float *__restrict__ Mn, uint64_t I, float *Ms, Body body) {
+    using S = SolveShape<R>;
+    constexpr int D = S::kDepth;
+    const uint64_t ntiles = (I + S::kTR - 1) / S::kTR;
+    const uint64_t stride = gridDim.x;
+    float4 q[D];
+#pragma unroll
+    for (int j = 0; j < D; j++) q[j] = load_tile<R>(Mn, I, blockIdx.x + j * stride);
+    for (uint64_t t0 = blockIdx.x; t0 < ntiles; t0 += D * stride) {
+#pragma unroll
+        for (int j = 0; j < D; j++) {
+            const uint64_t tile = t0 + j * stride;
+            if (tile >= ntiles) break;  // same for the whole block
+            reinterpret_cast<float4 *>(Ms)[threadIdx.x] = q[j];
+            q[j] = load_tile<R>(Mn, I, tile + D * stride);
+            __syncthreads();
+            body(tile);
+            __syncthreads();
+        }
+    }
 }
 
 template <int R>
@@ -344,17 +372,13 @@ __global__ __launch_bounds__(kT) void solve_colsq_k(const float *__restrict__ Mn
 #pragma unroll
     for (int k = 0; k < R; k++) vc[k] = Vinv[k * R + c];
     double acc = 0.0;
-    const uint64_t ntiles = (I + S::kTR - 1) / S::kTR;
-    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        stage_rows<R>(Mn, I, tile * S::kTR, Ms);
-        __syncthreads();
+    for_each_tile<R>(Mn, I, Ms, [&](uint64_t) {
 #pragma unroll
         for (int q = 0; q < S::kRPT; q++) {
             const double a = row_dot<R>(Ms, rg + S::kRG * q, vc);
             acc = fma(a, a, acc);
         }
-        __syncthreads();
-    }
+    });
     red[threadIdx.x] = acc;
     __syncthreads();
     if (threadIdx.x < R) {
@@ -363,6 +387,18 @@ __global__ __launch_bounds__(kT) void solve_colsq_k(const float *__restrict__ Mn
         colsq_part[(uint64_t)blockIdx.x * R + threadIdx.x] = s;
     }
 }
+
+// Register blocking of the Gram accumulation: thread (slice s, sub-block b)
+// sums the 4x4 sub-block b of A^T A over the tile rows s, s + kS, ...  Each
+// row then costs four 16-byte LDS reads for 16 FMAs.
+template <int R>
+struct GramShape {
+    static constexpr int kB = R / 4;                 // sub-blocks per side
+    static constexpr int kNB = kB * kB;              // sub-blocks
+    static_assert(kT % kNB == 0, "sub-blocks divide the block");
+    static constexpr int kS = kT / kNB;              // row slices
+    static constexpr int kEPT = (R * R + kT - 1) / kT;  // Gram entries per thread in the final fold
+};
 
 // Pass 2: A(i, c) = store(solve(i, c) / lambda_c); per-block partial Gram of
 // the stored rows, and (inner_part != nullptr) the partial inner products
@@ -373,26 +409,25 @@ __global__ __launch_bounds__(kT) void normalize_gram_k(const float *__restrict__
                                                        void *__restrict__ A, double *__restrict__ gram_part,
                                                        double *__restrict__ inner_part, const int *status) {
     using S = SolveShape<R>;
+    using GS = GramShape<R>;
     constexpr int TR = S::kTR;
-    constexpr int EPT = (R * R + kT - 1) / kT;  // Gram entries per thread
     __shared__ __align__(16) float Ms[TR * R];
-    __shared__ double As[TR * R];
+    __shared__ __align__(16) double As[TR * R];
     __shared__ double red[kT / 64];
     if (*status) return;
     const int c = threadIdx.x % R, rg = threadIdx.x / R;
+    const int blk = threadIdx.x % GS::kNB, slice = threadIdx.x / GS::kNB;
+    const int bi = blk / GS::kB, bj = blk % GS::kB;
     double vc[R];
 #pragma unroll
     for (int k = 0; k < R; k++) vc[k] = Vinv[k * R + c];
     const double lam = lambda[c];
-    double g[EPT];
+    double g[16];
 #pragma unroll
-    for (int j = 0; j < EPT; j++) g[j] = 0.0;
+    for (int j = 0; j < 16; j++) g[j] = 0.0;
     double inner = 0.0;
-    const uint64_t ntiles = (I + TR - 1) / TR;
-    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for_each_tile<R>(Mn, I, Ms, [&](uint64_t tile) {
         const uint64_t r0 = tile * TR;
-        stage_rows<R>(Mn, I, r0, Ms);
-        __syncthreads();
 #pragma unroll
         for (int q = 0; q < S::kRPT; q++) {
             const int r = rg + S::kRG * q;
@@ -415,23 +450,53 @@ __global__ __launch_bounds__(kT) void normalize_gram_k(const float *__restrict__
             As[r * R + c] = stored;
         }
         __syncthreads();
+        for (int r = slice; r < TR; r += GS::kS) {
+            const double2 *row = reinterpret_cast<const double2 *>(As + r * R);
+            const double2 x0 = row[2 * bi], x1 = row[2 * bi + 1];
+            const double2 y0 = row[2 * bj], y1 = row[2 * bj + 1];
+            const double x[4] = {x0.x, x0.y, x1.x, x1.y}, y[4] = {y0.x, y0.y, y1.x, y1.y};
 #pragma unroll
-        for (int j = 0; j < EPT; j++) {
-            const int e = threadIdx.x + j * kT;
-            if (e < R * R) {
-                const int a = e / R, b = e - a * R;
-                double sum = g[j];
-                for (int r = 0; r < TR; r++) sum = fma(As[r * R + a], As[r * R + b], sum);
-                g[j] = sum;
-            }
+            for (int u = 0; u < 4; u++)
+#pragma unroll
+                for (int v = 0; v < 4; v++) g[4 * u + v] = fma(x[u], y[v], g[4 * u + v]);
         }
-        __syncthreads();
-    }
+    });
+    // fold the slices' partial sums in slice order, a tile's worth of slices
+    // at a time through As, into entries threadIdx.x + j * kT of the block's Gram
     double *P = gram_part + (uint64_t)blockIdx.x * R * R;
+    if constexpr (GS::kS == 1) {
 #pragma unroll
-    for (int j = 0; j < EPT; j++) {
-        const int e = threadIdx.x + j * kT;
-        if (e < R * R) P[e] = g[j];
+        for (int u = 0; u < 4; u++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) P[(4 * bi + u) * R + 4 * bj + v] = g[4 * u + v];
+    } else {
+        constexpr int kPer = (TR * R) / (R * R);  // slices per round
+        static_assert(GS::kS % kPer == 0, "whole rounds");
+        double tot[GS::kEPT];
+#pragma unroll
+        for (int j = 0; j < GS::kEPT; j++) tot[j] = 0.0;
+        for (int s0 = 0; s0 < GS::kS; s0 += kPer) {
+            if (slice >= s0 && slice < s0 + kPer) {
+                double *dst = As + (slice - s0) * R * R;
+#pragma unroll
+                for (int u = 0; u < 4; u++)
+#pragma unroll
+                    for (int v = 0; v < 4; v++) dst[(4 * bi + u) * R + 4 * bj + v] = g[4 * u + v];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < GS::kEPT; j++) {
+                const int e = threadIdx.x + j * kT;
+                if (e < R * R)
+                    for (int k = 0; k < kPer; k++) tot[j] += As[k * R * R + e];
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int j = 0; j < GS::kEPT; j++) {
+            const int e = threadIdx.x + j * kT;
+            if (e < R * R) P[e] = tot[j];
+        }
     }
     if (!inner_part) return;
     for (int off = 32; off >= 1; off >>= 1) inner += __shfl_xor(inner, off);
@@ -489,24 +554,44 @@ struct AlsWs {
     int *status;
 };
 
-constexpr int kSolveBlocks = 512;  // blocks of the rank-specialized passes
+// Blocks of the rank-specialized passes: as many as are resident at once
+// (occupancy x compute units, at most kMaxSolveBlocks), so that each block
+// streams many tiles with several of them in flight.
+constexpr int kMaxSolveBlocks = 2048;
+
+struct SolveGrid {
+    int solve = 1, norm = 1;
+};
+
+template <int R>
+int solve_grid(SolveGrid *g) {
+    int dev = 0, cus = 0, a = 0, b = 0;
+    ALTO_HIP(hipGetDevice(&dev));
+    ALTO_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    ALTO_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, (const void *)solve_colsq_k<R>, kT, 0));
+    ALTO_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void *)normalize_gram_k<R>, kT, 0));
+    g->solve = std::clamp(a * cus, 1, kMaxSolveBlocks);
+    g->norm = std::clamp(b * cus, 1, kMaxSolveBlocks);
+    return ALTO_OK;
+}
 
 // One mode update after its MTTKRP (Mn), rank-specialized; see above.
 template <int R>
-int update_mode_r(AlsWs &w, uint64_t I, int prec, void *factor, double *lambda, bool last, int *nparts_inner,
-                  hipStream_t s) {
+int update_mode_r(AlsWs &w, const SolveGrid &grid, uint64_t I, int prec, void *factor, double *lambda, bool last,
+                  int *nparts_inner, hipStream_t s) {
     using S = SolveShape<R>;
     const uint64_t ntiles = (I + S::kTR - 1) / S::kTR;
-    const int nb = (int)std::max<uint64_t>(1, std::min<uint64_t>(kSolveBlocks, ntiles));
-    solve_colsq_k<R><<<nb, kT, 0, s>>>(w.Mn, w.Vinv, I, w.colsq, w.status);
-    sum_slices_partial_k<<<dim3((R + kT - 1) / kT, kSlices), kT, 0, s>>>(w.colsq, nb, R, w.tmp, w.status);
+    const int nbs = (int)std::max<uint64_t>(1, std::min<uint64_t>(grid.solve, ntiles));
+    const int nbn = (int)std::max<uint64_t>(1, std::min<uint64_t>(grid.norm, ntiles));
+    solve_colsq_k<R><<<nbs, kT, 0, s>>>(w.Mn, w.Vinv, I, w.colsq, w.status);
+    sum_slices_partial_k<<<dim3((R + kT - 1) / kT, kSlices), kT, 0, s>>>(w.colsq, nbs, R, w.tmp, w.status);
     sum_slices_k<<<(R + kT - 1) / kT, kT, 0, s>>>(w.tmp, R, lambda, 1, w.status);
-    normalize_gram_k<R><<<nb, kT, 0, s>>>(w.Mn, w.Vinv, lambda, I, prec, factor, w.parts,
-                                          last ? w.inner : nullptr, w.status);
+    normalize_gram_k<R><<<nbn, kT, 0, s>>>(w.Mn, w.Vinv, lambda, I, prec, factor, w.parts,
+                                           last ? w.inner : nullptr, w.status);
     const int64_t RR = (int64_t)R * R;
-    sum_slices_partial_k<<<dim3((unsigned)((RR + kT - 1) / kT), kSlices), kT, 0, s>>>(w.parts, nb, RR, w.tmp,
+    sum_slices_partial_k<<<dim3((unsigned)((RR + kT - 1) / kT), kSlices), kT, 0, s>>>(w.parts, nbn, RR, w.tmp,
                                                                                   w.status);
-    *nparts_inner = nb;
+    *nparts_inner = nbn;
     ALTO_HIP(hipGetLastError());
     return ALTO_OK;
 }
@@ -548,6 +633,7 @@ int cp_als_impl(alto_tensor *t, int R, int iters, int prec, void *const *factors
     for (int n = 0; n < N; n++) maxI = std::max(maxI, t->dims[n]);
     const int RR = R * R;
     const int P = parts_for(maxI);
+    int rc0 = ALTO_OK;
     // the MTTKRP output and the FP64 work arrays live in their own allocation
     // (the tensor workspace may be regrown by a re-partition)
     size_t off = 0;
@@ -556,11 +642,22 @@ int cp_als_impl(alto_tensor *t, int R, int iters, int prec, void *const *factors
         off += align256(b);
         return o;
     };
+    const bool special = R == 8 || R == 16 || R == 32 || R == 64;
+    SolveGrid grid;
+    if (special) {
+        switch (R) {
+            case 8: rc0 = solve_grid<8>(&grid); break;
+            case 16: rc0 = solve_grid<16>(&grid); break;
+            case 32: rc0 = solve_grid<32>(&grid); break;
+            default: rc0 = solve_grid<64>(&grid); break;
+        }
+        if (rc0) return rc0;
+    }
     const size_t oMn = take(sizeof(float) * maxI * R),
                  oG = take(sizeof(double) * N * RR),
-                 oVi = take(sizeof(double) * RR), oP = take(sizeof(double) * (size_t)std::max(P, kSolveBlocks) * RR),
-                 oC = take(sizeof(double) * (size_t)std::max(kMaxParts, kSolveBlocks) * R),
-                 oT = take(sizeof(double) * (size_t)kSlices * RR), oI = take(sizeof(double) * 2048),
+                 oVi = take(sizeof(double) * RR), oP = take(sizeof(double) * (size_t)std::max(P, grid.norm) * RR),
+                 oC = take(sizeof(double) * (size_t)std::max(kMaxParts, grid.solve) * R),
+                 oT = take(sizeof(double) * (size_t)kSlices * RR), oI = take(sizeof(double) * std::max(2048, kMaxSolveBlocks)),
                  oF = take(sizeof(double) * std::max(1, iters)), oS = take(sizeof(int));
     char *base = nullptr;
     ALTO_HIP(hipMalloc(&base, off));
@@ -596,7 +693,6 @@ int cp_als_impl(alto_tensor *t, int R, int iters, int prec, void *const *factors
     if (neq_lds > 64 * 1024)
         ALS_HIP(hipFuncSetAttribute((const void *)normal_eq_gj_k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)neq_lds));
-    const bool special = R == 8 || R == 16 || R == 32 || R == 64;
     for (int it = 0; it < iters; it++) {
         for (int n = 0; n < N; n++) {
             const uint64_t I = t->dims[n];
@@ -607,10 +703,10 @@ int cp_als_impl(alto_tensor *t, int R, int iters, int prec, void *const *factors
             if (special) {
                 int nin = 0;
                 switch (R) {
-                    case 8: rc = update_mode_r<8>(w, I, prec, factors[n], lambda, last, &nin, s); break;
-                    case 16: rc = update_mode_r<16>(w, I, prec, factors[n], lambda, last, &nin, s); break;
-                    case 32: rc = update_mode_r<32>(w, I, prec, factors[n], lambda, last, &nin, s); break;
-                    default: rc = update_mode_r<64>(w, I, prec, factors[n], lambda, last, &nin, s); break;
+                    case 8: rc = update_mode_r<8>(w, grid, I, prec, factors[n], lambda, last, &nin, s); break;
+                    case 16: rc = update_mode_r<16>(w, grid, I, prec, factors[n], lambda, last, &nin, s); break;
+                    case 32: rc = update_mode_r<32>(w, grid, I, prec, factors[n], lambda, last, &nin, s); break;
+                    default: rc = update_mode_r<64>(w, grid, I, prec, factors[n], lambda, last, &nin, s); break;
                 }
                 if (rc) return done(rc);
                 sum_slices_k<<<(unsigned)((RR + kT - 1) / kT), kT, 0, s>>>(w.tmp, RR, w.G + (size_t)n * RR, 0,
