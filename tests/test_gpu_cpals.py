@@ -79,9 +79,9 @@ def test_cp_als_zero_iterations_and_errors():
     t.close()
 
 
-@pytest.mark.parametrize("R", [5, 8, 32, 64, 96, 160])
+@pytest.mark.parametrize("R", [5, 8, 16, 32, 64, 96, 160])
 def test_cp_als_ranks_match_oracle(R):
-    # ranks with a specialized update (8, 32, 64) and the generic one, with
+    # ranks with a specialized update (8, 16, 32, 64) and the generic one, with
     # the normal equations in LDS (R <= 128) and in device memory (160)
     rec = synth.scaled(synth.WORKLOADS["uniform3_1000x800x600_100k"], 30_000)
     coords, vals = synth.coo(rec)
@@ -92,6 +92,26 @@ def test_cp_als_ranks_match_oracle(R):
     fd = factors_dev(init)
     lam, fit = t.cp_als(fd, 3)
     print("R", R, "fit", fit, "oracle", ofit, flush=True)
+    assert np.all(np.abs(fit - ofit) <= 1e-5)
+    assert np.allclose(lam.cpu().numpy(), olam, rtol=1e-3)
+    for f, a in zip(fd, oA):
+        assert rel_fro(f.cpu().numpy(), a) <= 1e-3
+    t.close()
+
+
+@pytest.mark.parametrize("R,rows", [(16, 330_001), (32, 200_003), (64, 60_001)])
+def test_cp_als_tall_mode_matches_oracle(R, rows):
+    # a tall mode: the blocks of the row-solve passes stream more tiles than
+    # the loads they keep in flight (on a 256-CU GPU), with a ragged last tile
+    rec = synth.Recipe("tall", (rows, 300, 200), 150_000, (0.8, 0, 0), seed=11)
+    coords, vals = synth.coo(rec)
+    c, v = to_dev(coords, vals)
+    t = alto.AltoTensor.build(c, v, rec.dims)
+    init = synth.factors(rec.seed + 1, rec.dims, R)
+    oA, olam, ofit = oracle.cp_als(rec.dims, coords, vals, init, 2)
+    fd = factors_dev(init)
+    lam, fit = t.cp_als(fd, 2)
+    print("tall R", R, "fit", fit, "oracle", ofit, flush=True)
     assert np.all(np.abs(fit - ofit) <= 1e-5)
     assert np.allclose(lam.cpu().numpy(), olam, rtol=1e-3)
     for f, a in zip(fd, oA):
