@@ -7,6 +7,7 @@
 // round-to-nearest-even).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "common.h"
 
@@ -232,6 +233,8 @@ __global__ __launch_bounds__(kT) void fit_k(const double *__restrict__ G, int N,
 // the squared diagonal of its Cholesky factor), so a pivot <= 0 is the same
 // failure test as a failed Cholesky factorization; the ridge retry follows.
 // The matrix lives in LDS when R <= 128, else it is inverted in place in Vinv.
+constexpr int kGjPer = 16;  // matrix elements per thread held as (row, column) pairs
+
 __global__ __launch_bounds__(1024) void normal_eq_gj_k(const double *__restrict__ G, int N, int R, int skip,
                                                        double *__restrict__ Vinv, int *status) {
     extern __shared__ double shm[];
@@ -243,6 +246,16 @@ __global__ __launch_bounds__(1024) void normal_eq_gj_k(const double *__restrict_
     double *colk = shm + (in_lds ? RR : 0);
     double *rowk = colk + R;
     const int nt = blockDim.x;
+    // the (row, column) of the thread's elements, computed once when there
+    // are at most kGjPer of them (row R marks none)
+    const bool few = RR <= kGjPer * nt;
+    int ei[kGjPer], ej[kGjPer];
+#pragma unroll
+    for (int q = 0; q < kGjPer; q++) {
+        const int e = threadIdx.x + q * nt;
+        ei[q] = e < RR ? e / R : R;
+        ej[q] = e < RR ? e % R : 0;
+    }
     bool bad = false;
     for (int attempt = 0; attempt < 2; attempt++) {
         if (threadIdx.x == 0) {
@@ -277,13 +290,19 @@ __global__ __launch_bounds__(1024) void normal_eq_gj_k(const double *__restrict_
                 rowk[i] = A[k * R + i] * rp;
             }
             __syncthreads();
-            for (int e = threadIdx.x; e < RR; e += nt) {
-                const int i = e / R, j = e - i * R;
+            auto update = [&](int e, int i, int j) {
                 double v;
                 if (i == k) v = j == k ? rp : rowk[j];
                 else if (j == k) v = -colk[i] * rp;
                 else v = A[e] - colk[i] * rowk[j];
                 A[e] = v;
+            };
+            if (few) {
+#pragma unroll
+                for (int q = 0; q < kGjPer; q++)
+                    if (ei[q] < R) update(threadIdx.x + q * nt, ei[q], ej[q]);
+            } else {
+                for (int e = threadIdx.x; e < RR; e += nt) update(e, e / R, e % R);
             }
             __syncthreads();
         }
@@ -509,6 +528,210 @@ __global__ __launch_bounds__(kT) void normalize_gram_k(const float *__restrict__
     }
 }
 
+// ---------------------------------------------------------------- FP64 matrix cores (R = 16, 32)
+// The row solves as 16-row tile products on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64): S = Mn_tile V^-1, then the Gram of the stored
+// tile, S_st^T S_st, from the same registers.  Every wave streams its own
+// tiles (no LDS, no barriers in the loop).  Operand layout of the
+// instruction (16x4 A, 4x16 B, 16x16 D): lane l holds A(l%16, l/16) and
+// B(l/16, l%16); register q of D holds D(4q + l/16, l%16).  A lane loads
+// the float4s at columns 4(l/16 + 4t) .. +3 of tile row l%16; the solve's
+// contraction index runs over them in that order, and the matching rows
+// of V^-1 sit in registers.  Register q of the solve's output block then
+// holds rows 4q + l/16 of the tile: exactly the A and B operands of the
+// Gram product over those four rows.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+template <int R>
+struct MfShape {
+    static_assert(R == 16 || R == 32, "matrix-core row solves for R = 16, 32");
+    static constexpr int kB = R / 16;          // 16-column blocks; also float4 loads per lane per tile
+    static constexpr int kWaves = kT / 64;
+};
+
+template <int R>
+__device__ __forceinline__ void mf_load(const float *__restrict__ Mn, uint64_t I, uint64_t tile, int lane,
+                                        float4 (&q)[MfShape<R>::kB]) {
+    const uint64_t row = tile * 16 + (lane & 15);
+#pragma unroll
+    for (int t = 0; t < MfShape<R>::kB; t++)
+        q[t] = row < I ? *reinterpret_cast<const float4 *>(Mn + row * R + 4 * ((lane >> 4) + 4 * t))
+                       : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+template <int R>
+__device__ __forceinline__ void mf_vinv(const double *__restrict__ Vinv, int lane,
+                                        double (&vb)[MfShape<R>::kB][4][MfShape<R>::kB]) {
+#pragma unroll
+    for (int t = 0; t < MfShape<R>::kB; t++)
+#pragma unroll
+        for (int e = 0; e < 4; e++)
+#pragma unroll
+            for (int cb = 0; cb < MfShape<R>::kB; cb++)
+                vb[t][e][cb] = Vinv[(4 * ((lane >> 4) + 4 * t) + e) * R + 16 * cb + (lane & 15)];
+}
+
+// s[cb][q] = S(4q + l/16, 16 cb + l%16) of the tile
+template <int R>
+__device__ __forceinline__ void mf_solve(const float4 (&q)[MfShape<R>::kB],
+                                         const double (&vb)[MfShape<R>::kB][4][MfShape<R>::kB],
+                                         dbl4 (&s)[MfShape<R>::kB]) {
+    constexpr int B = MfShape<R>::kB;
+#pragma unroll
+    for (int cb = 0; cb < B; cb++) s[cb] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < B; t++) {
+        const double a[4] = {(double)q[t].x, (double)q[t].y, (double)q[t].z, (double)q[t].w};
+#pragma unroll
+        for (int e = 0; e < 4; e++)
+#pragma unroll
+            for (int cb = 0; cb < B; cb++) s[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[e], vb[t][e][cb], s[cb], 0, 0, 0);
+    }
+}
+
+// Runs body(tile, q) over the wave's tiles (global wave w: tiles w, w + W,
+// ...), with the next tile's loads in flight.
+template <int R, class Body>
+__device__ __forceinline__ void mf_for_each_tile(const float *__restrict__ Mn, uint64_t I, int lane, Body body) {
+    constexpr int B = MfShape<R>::kB;
+    const uint64_t nw = (uint64_t)gridDim.x * MfShape<R>::kWaves;
+    const uint64_t w = (uint64_t)blockIdx.x * MfShape<R>::kWaves + threadIdx.x / 64;
+    const uint64_t ntiles = (I + 15) / 16;
+    float4 q[B];
+    mf_load<R>(Mn, I, w, lane, q);
+    for (uint64_t tile = w; tile < ntiles; tile += nw) {
+        float4 cur[B];
+#pragma unroll
+        for (int t = 0; t < B; t++) cur[t] = q[t];
+        mf_load<R>(Mn, I, tile + nw, lane, q);
+        body(tile, cur);
+    }
+}
+
+// Pass 1 on the matrix cores: per-block column sums of squares of S.
+template <int R>
+__global__ __launch_bounds__(kT) void solve_colsq_mf_k(const float *__restrict__ Mn, const double *__restrict__ Vinv,
+                                                       uint64_t I, double *__restrict__ colsq_part,
+                                                       const int *status) {
+    constexpr int B = MfShape<R>::kB;
+    __shared__ double red[MfShape<R>::kWaves][R];
+    if (*status) return;
+    const int lane = __lane_id(), wave = threadIdx.x / 64;
+    double vb[B][4][B];
+    mf_vinv<R>(Vinv, lane, vb);
+    double cs[B];
+#pragma unroll
+    for (int cb = 0; cb < B; cb++) cs[cb] = 0.0;
+    mf_for_each_tile<R>(Mn, I, lane, [&](uint64_t, const float4 (&q)[B]) {
+        dbl4 s[B];
+        mf_solve<R>(q, vb, s);
+#pragma unroll
+        for (int cb = 0; cb < B; cb++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) cs[cb] = fma(s[cb][r], s[cb][r], cs[cb]);
+    });
+#pragma unroll
+    for (int cb = 0; cb < B; cb++) {
+        cs[cb] += __shfl_xor(cs[cb], 16);
+        cs[cb] += __shfl_xor(cs[cb], 32);
+        if (lane < 16) red[wave][16 * cb + lane] = cs[cb];
+    }
+    __syncthreads();
+    if (threadIdx.x < R) {
+        double sum = 0.0;
+        for (int w = 0; w < MfShape<R>::kWaves; w++) sum += red[w][threadIdx.x];
+        colsq_part[(uint64_t)blockIdx.x * R + threadIdx.x] = sum;
+    }
+}
+
+// Pass 2 on the matrix cores: A = store(S / lambda), per-block partial Gram
+// of the stored rows, and (inner_part != nullptr) the partial inner products
+// sum_i lambda_c Mn(i, c) A(i, c).
+template <int R>
+__global__ __launch_bounds__(kT) void normalize_gram_mf_k(const float *__restrict__ Mn,
+                                                          const double *__restrict__ Vinv,
+                                                          const double *__restrict__ lambda, uint64_t I, int prec,
+                                                          void *__restrict__ A, double *__restrict__ gram_part,
+                                                          double *__restrict__ inner_part, const int *status) {
+    constexpr int B = MfShape<R>::kB;
+    constexpr int W = MfShape<R>::kWaves;
+    __shared__ double red[W][R * R];
+    __shared__ double ired[W];
+    if (*status) return;
+    const int lane = __lane_id(), wave = threadIdx.x / 64;
+    double vb[B][4][B];
+    mf_vinv<R>(Vinv, lane, vb);
+    double lam[B];
+#pragma unroll
+    for (int cb = 0; cb < B; cb++) lam[cb] = lambda[16 * cb + (lane & 15)];
+    dbl4 g[B][B];
+#pragma unroll
+    for (int a = 0; a < B; a++)
+#pragma unroll
+        for (int b = 0; b < B; b++) g[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+    double inner = 0.0;
+    const bool with_inner = inner_part != nullptr;
+    mf_for_each_tile<R>(Mn, I, lane, [&](uint64_t tile, const float4 (&q)[B]) {
+        dbl4 s[B];
+        mf_solve<R>(q, vb, s);
+        dbl4 st[B];
+#pragma unroll
+        for (int cb = 0; cb < B; cb++) {
+            const int c = 16 * cb + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const uint64_t row = tile * 16 + 4 * r + (lane >> 4);
+                const double a = lam[cb] > 0.0 ? s[cb][r] / lam[cb] : s[cb][r];
+                const float f = (float)a;
+                double stored = 0.0;
+                if (row < I) {
+                    const uint64_t e = row * R + c;
+                    if (prec == ALTO_PREC_BF16) {
+                        const uint16_t b = f32_to_bf16_rne(f);
+                        reinterpret_cast<uint16_t *>(A)[e] = b;
+                        stored = (double)__uint_as_float((uint32_t)b << 16);
+                    } else {
+                        reinterpret_cast<float *>(A)[e] = f;
+                        stored = (double)f;
+                    }
+                    if (with_inner) inner += lam[cb] * (double)Mn[e] * stored;
+                }
+                st[cb][r] = stored;
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < B; a++)
+#pragma unroll
+            for (int b = 0; b < B; b++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) g[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(st[a][r], st[b][r], g[a][b], 0, 0, 0);
+    });
+    // block (a, b), register q of lane l: Gram(16a + 4q + l/16, 16b + l%16)
+#pragma unroll
+    for (int a = 0; a < B; a++)
+#pragma unroll
+        for (int b = 0; b < B; b++)
+#pragma unroll
+            for (int qq = 0; qq < 4; qq++)
+                red[wave][(16 * a + 4 * qq + (lane >> 4)) * R + 16 * b + (lane & 15)] = g[a][b][qq];
+    if (with_inner) {
+        for (int off = 32; off >= 1; off >>= 1) inner += __shfl_xor(inner, off);
+        if (lane == 0) ired[wave] = inner;
+    }
+    __syncthreads();
+    double *P = gram_part + (uint64_t)blockIdx.x * R * R;
+    for (int e = threadIdx.x; e < R * R; e += kT) {
+        double sum = 0.0;
+        for (int w = 0; w < W; w++) sum += red[w][e];
+        P[e] = sum;
+    }
+    if (with_inner && threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int w = 0; w < W; w++) sum += ired[w];
+        inner_part[blockIdx.x] = sum;
+    }
+}
+
 // Fixed-order reduction of partials in two levels: slice y of the grid sums
 // partials [y*P/S, (y+1)*P/S) into tmp[y], then sum_slices_k adds the S
 // slices.  out[e] = sum_p partials[p][e] for every launch size.
@@ -563,13 +786,34 @@ struct SolveGrid {
     int solve = 1, norm = 1;
 };
 
+// R = 16 and 32 run the row solves on the FP64 matrix cores unless
+// ALTO_CPALS_MFMA=0 asks for the vector kernels.
+template <int R>
+constexpr bool has_mf() { return R == 16 || R == 32; }
+
+bool use_mf() {
+    static const bool on = [] {
+        const char *e = getenv("ALTO_CPALS_MFMA");
+        return !(e && *e && atol(e) == 0);
+    }();
+    return on;
+}
+
 template <int R>
 int solve_grid(SolveGrid *g) {
     int dev = 0, cus = 0, a = 0, b = 0;
     ALTO_HIP(hipGetDevice(&dev));
     ALTO_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    ALTO_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, (const void *)solve_colsq_k<R>, kT, 0));
-    ALTO_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void *)normalize_gram_k<R>, kT, 0));
+    if constexpr (has_mf<R>()) {
+        if (use_mf()) {
+            ALTO_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, (const void *)solve_colsq_mf_k<R>, kT, 0));
+            ALTO_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void *)normalize_gram_mf_k<R>, kT, 0));
+        }
+    }
+    if (a == 0) {
+        ALTO_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, (const void *)solve_colsq_k<R>, kT, 0));
+        ALTO_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void *)normalize_gram_k<R>, kT, 0));
+    }
     g->solve = std::clamp(a * cus, 1, kMaxSolveBlocks);
     g->norm = std::clamp(b * cus, 1, kMaxSolveBlocks);
     return ALTO_OK;
@@ -579,15 +823,23 @@ int solve_grid(SolveGrid *g) {
 template <int R>
 int update_mode_r(AlsWs &w, const SolveGrid &grid, uint64_t I, int prec, void *factor, double *lambda, bool last,
                   int *nparts_inner, hipStream_t s) {
-    using S = SolveShape<R>;
-    const uint64_t ntiles = (I + S::kTR - 1) / S::kTR;
-    const int nbs = (int)std::max<uint64_t>(1, std::min<uint64_t>(grid.solve, ntiles));
-    const int nbn = (int)std::max<uint64_t>(1, std::min<uint64_t>(grid.norm, ntiles));
-    solve_colsq_k<R><<<nbs, kT, 0, s>>>(w.Mn, w.Vinv, I, w.colsq, w.status);
+    bool mf = false;
+    if constexpr (has_mf<R>()) mf = use_mf();
+    // work units: 16-row tiles per wave of 4 (matrix cores), or tiles of 1024 / R rows
+    const uint64_t units = mf ? ((I + 15) / 16 + kT / 64 - 1) / (kT / 64) : (I + SolveShape<R>::kTR - 1) / SolveShape<R>::kTR;
+    const int nbs = (int)std::max<uint64_t>(1, std::min<uint64_t>(grid.solve, units));
+    const int nbn = (int)std::max<uint64_t>(1, std::min<uint64_t>(grid.norm, units));
+    double *inner = last ? w.inner : nullptr;
+    if constexpr (has_mf<R>()) {
+        if (mf) solve_colsq_mf_k<R><<<nbs, kT, 0, s>>>(w.Mn, w.Vinv, I, w.colsq, w.status);
+    }
+    if (!mf) solve_colsq_k<R><<<nbs, kT, 0, s>>>(w.Mn, w.Vinv, I, w.colsq, w.status);
     sum_slices_partial_k<<<dim3((R + kT - 1) / kT, kSlices), kT, 0, s>>>(w.colsq, nbs, R, w.tmp, w.status);
     sum_slices_k<<<(R + kT - 1) / kT, kT, 0, s>>>(w.tmp, R, lambda, 1, w.status);
-    normalize_gram_k<R><<<nbn, kT, 0, s>>>(w.Mn, w.Vinv, lambda, I, prec, factor, w.parts,
-                                           last ? w.inner : nullptr, w.status);
+    if constexpr (has_mf<R>()) {
+        if (mf) normalize_gram_mf_k<R><<<nbn, kT, 0, s>>>(w.Mn, w.Vinv, lambda, I, prec, factor, w.parts, inner, w.status);
+    }
+    if (!mf) normalize_gram_k<R><<<nbn, kT, 0, s>>>(w.Mn, w.Vinv, lambda, I, prec, factor, w.parts, inner, w.status);
     const int64_t RR = (int64_t)R * R;
     sum_slices_partial_k<<<dim3((unsigned)((RR + kT - 1) / kT), kSlices), kT, 0, s>>>(w.parts, nbn, RR, w.tmp,
                                                                                   w.status);
