@@ -317,6 +317,100 @@ __global__ __launch_bounds__(1024) void normal_eq_gj_k(const double *__restrict_
         for (int e = threadIdx.x; e < RR; e += nt) Vinv[e] = A[e];
 }
 
+// The same elimination in one wave for R <= 32, with the matrix in
+// registers: lane l holds column l % 32 of rows l / 32 + 2q (q < 16); only
+// the pivot row and column go through LDS.  Each step reads all it needs
+// first and then updates every element with selects, so the LDS round trips
+// of a step overlap.  Per element the operations and their order are those
+// of normal_eq_gj_k (only the retry's trace is summed in another order).
+__global__ __launch_bounds__(64) void normal_eq_gj_wave_k(const double *__restrict__ G, int N, int R, int skip,
+                                                          double *__restrict__ Vinv, int *status) {
+    __shared__ double rowk[32], colk[32];
+    if (*status) return;
+    const int RR = R * R;
+    const int lane = threadIdx.x, j = lane & 31, h = lane >> 5;
+    double a[16];
+    // V = Hadamard product of the Grams, multiplied in mode order; all of a
+    // Gram's loads are issued together
+    auto build = [&](double ridge) {
+#pragma unroll
+        for (int q = 0; q < 16; q++) a[q] = 1.0;
+        for (int m = 0; m < N; m++) {
+            if (m == skip) continue;
+            double g[16];
+#pragma unroll
+            for (int q = 0; q < 16; q++) {
+                const int i = h + 2 * q;
+                g[q] = i < R && j < R ? G[(int64_t)m * RR + i * R + j] : 1.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 16; q++) a[q] *= g[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 16; q++) a[q] += h + 2 * q == j ? ridge : 0.0;
+    };
+    bool bad = false;
+    for (int attempt = 0; attempt < 2; attempt++) {
+        double ridge = 0.0;
+        if (attempt > 0) {  // the trace is only needed for the retry
+            double d = 0.0;
+            if (lane < R) {
+                d = 1.0;
+                for (int m = 0; m < N; m++)
+                    if (m != skip) d *= G[(int64_t)m * RR + lane * R + lane];
+            }
+            for (int off = 32; off >= 1; off >>= 1) d += __shfl_xor(d, off);
+            ridge = 1e-10 * d / R;
+        }
+        build(ridge);
+        bad = false;
+        for (int k = 0; k < R; k++) {
+            __syncthreads();  // the previous step's reads are done
+            // row k lives in lanes with h == k % 2, register k / 2
+            double rk = 0.0;
+#pragma unroll
+            for (int q = 0; q < 16; q++) {
+                rk = q == (k >> 1) ? a[q] : rk;
+            }
+            if (h == (k & 1) && j < R) rowk[j] = rk;
+            if (j == k) {
+#pragma unroll
+                for (int q = 0; q < 16; q++)
+                    if (h + 2 * q < R) colk[h + 2 * q] = a[q];
+            }
+            __syncthreads();
+            const double piv = rowk[k];
+            if (!(piv > 0.0)) {  // the same value in every lane
+                bad = true;
+                break;
+            }
+            double ci[16];
+#pragma unroll
+            for (int q = 0; q < 16; q++) ci[q] = h + 2 * q < R ? colk[h + 2 * q] : 0.0;
+            const double rp = 1.0 / piv;
+            const double rj = (j < R ? rowk[j] : 0.0) * rp;
+#pragma unroll
+            for (int q = 0; q < 16; q++) {
+                const int i = h + 2 * q;
+                const double other = a[q] - ci[q] * rj;
+                const double colv = -ci[q] * rp;
+                const double rowv = j == k ? rp : rj;
+                a[q] = i == k ? rowv : (j == k ? colv : other);
+            }
+        }
+        if (!bad) break;
+    }
+    if (bad) {
+        if (lane == 0) *status = 1;
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < 16; q++) {
+        const int i = h + 2 * q;
+        if (i < R && j < R) Vinv[i * R + j] = a[q];
+    }
+}
+
 template <int R>
 struct SolveShape {
     static constexpr int kRG = kT / R;       // row groups (threads per column)
@@ -745,7 +839,8 @@ __global__ __launch_bounds__(kT) void sum_slices_partial_k(const double *__restr
     const int y = blockIdx.y;
     const int p0 = (int)((int64_t)nparts * y / kSlices), p1 = (int)((int64_t)nparts * (y + 1) / kSlices);
     double s = 0.0;
-    for (int p = p0; p < p1; p++) s += partials[(int64_t)p * n + e];
+#pragma unroll 8
+    for (int p = p0; p < p1; p++) s += partials[(int64_t)p * n + e];  // loads overlap, adds in order
     tmp[(int64_t)y * n + e] = s;
 }
 
@@ -950,7 +1045,8 @@ int cp_als_impl(alto_tensor *t, int R, int iters, int prec, void *const *factors
             const uint64_t I = t->dims[n];
             rc = plan_and_run_mttkrp(t, (const void *const *)factors, R, prec, n, w.Mn, ex, s);
             if (rc) return done(rc);
-            normal_eq_gj_k<<<1, neq_threads, neq_lds, s>>>(w.G, N, R, n, w.Vinv, w.status);
+            if (R <= 32) normal_eq_gj_wave_k<<<1, 64, 0, s>>>(w.G, N, R, n, w.Vinv, w.status);
+            else normal_eq_gj_k<<<1, neq_threads, neq_lds, s>>>(w.G, N, R, n, w.Vinv, w.status);
             const bool last = n == N - 1;
             if (special) {
                 int nin = 0;
