@@ -83,6 +83,32 @@ int make_layout(alto_tensor *t, int key_bits_req) {
         }
         t->tab.nruns[n] = nr;
     }
+    // deposit tables: the index bits of each byte value of each coordinate byte
+    t->h_etab.clear();
+    {
+        int E = 0;
+        for (int n = 0; n < N; n++) {
+            t->tab.ebytes[n] = (uint8_t)((t->nbits[n] + 7) / 8);
+            t->tab.eoff[n] = (uint32_t)E;
+            E += t->tab.ebytes[n] * 256;
+        }
+        const size_t esz = (size_t)t->key_bits / 8;
+        t->tab.etab_entries = (size_t)E * esz <= kEncodeTableMax ? E : 0;
+        if (t->tab.etab_entries > 0) {
+            t->h_etab.assign((size_t)E * esz, 0);
+            for (int n = 0; n < N; n++)
+                for (int j = 0; j < t->tab.ebytes[n]; j++)
+                    for (int v = 0; v < 256; v++) {
+                        uint64_t e[2] = {0, 0};
+                        for (int b = 0; b < 8; b++) {
+                            const int k = 8 * j + b;
+                            if (k < t->nbits[n] && ((v >> b) & 1)) e[where[n][k] >> 6] |= 1ull << (where[n][k] & 63);
+                        }
+                        std::memcpy(&t->h_etab[((size_t)t->tab.eoff[n] + (size_t)j * 256 + v) * esz], e,
+                                    esz);  // little-endian entry ({lo, hi} for 128 bits)
+                    }
+        }
+    }
     // compact form: coordinate bit k of mode n lands at bit coff[n] + k
     int coff = 0;
     for (int n = 0; n < N; n++) {
@@ -579,6 +605,10 @@ int alto_build(const uint32_t *const *coords, const float *vals, int64_t nnz, co
             ALTO_TRY(hipMalloc(&t->ctab, t->h_ctab.size()));
             ALTO_TRY(hipMemcpyAsync(t->ctab, t->h_ctab.data(), t->h_ctab.size(), hipMemcpyHostToDevice, s));
         }
+        if (!t->h_etab.empty()) {
+            ALTO_TRY(hipMalloc(&t->etab, t->h_etab.size()));
+            ALTO_TRY(hipMemcpyAsync(t->etab, t->h_etab.data(), t->h_etab.size(), hipMemcpyHostToDevice, s));
+        }
         ALTO_TRY(hipMalloc(&t->vals, sizeof(float) * nnz));
         ALTO_TRY(hipMalloc(&keys_alt, kb * nnz));
         ALTO_TRY(hipMalloc(&vals_alt, sizeof(float) * nnz));
@@ -589,7 +619,7 @@ int alto_build(const uint32_t *const *coords, const float *vals, int64_t nnz, co
         ALTO_TRY(hipMemcpyAsync(t->vals, vals, sizeof(float) * nnz, hipMemcpyDeviceToDevice, s));
         CoordPtrs cp{};
         for (int n = 0; n < N; n++) cp.p[n] = coords[n];
-        rc = launch_encode(t->key_bits, cp, (const uint64_t *)dims_d, nnz, t->tab, t->keys, flag, s);
+        rc = launch_encode(t->key_bits, cp, (const uint64_t *)dims_d, nnz, t->tab, t->etab, t->keys, flag, s);
         if (rc) return fail(rc);
         int hflag = 0;
         ALTO_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -759,6 +789,7 @@ void alto_free(alto_tensor *t) {
     (void)hipFree(t->rep);
     (void)hipFree(t->keys);
     (void)hipFree(t->ctab);
+    (void)hipFree(t->etab);
     (void)hipFree(t->vals);
     (void)hipFree(t->ws);
     delete t;

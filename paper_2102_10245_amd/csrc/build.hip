@@ -144,6 +144,45 @@ __global__ __launch_bounds__(kThreads) void encode_k(CoordPtrs c, const uint64_t
     }
 }
 
+__device__ __forceinline__ void key_or(uint32_t &a, uint32_t b) { a |= b; }
+__device__ __forceinline__ void key_or(uint64_t &a, uint64_t b) { a |= b; }
+__device__ __forceinline__ void key_or(u128 &a, const u128 &b) {
+    a.lo |= b.lo;
+    a.hi |= b.hi;
+}
+
+// The same linearization through the deposit tables, staged in LDS once per
+// block: one table entry per coordinate byte, OR-ed into the index.  The
+// grid is capped so that every block streams many nonzeros.
+template <typename K>
+__global__ __launch_bounds__(kThreads) void encode_tab_k(CoordPtrs c, const uint64_t *__restrict__ dims, int64_t n,
+                                                         RunTable tab, const K *__restrict__ etab,
+                                                         K *__restrict__ keys, int *flag) {
+    extern __shared__ __align__(16) char dyn[];
+    K *const lt = reinterpret_cast<K *>(dyn);
+    for (int q = threadIdx.x; q < tab.etab_entries; q += kThreads) lt[q] = etab[q];
+    __syncthreads();
+    const int N = tab.N;
+    uint64_t dm[kMaxModes];
+#pragma unroll
+    for (int m = 0; m < kMaxModes; m++) dm[m] = m < N ? dims[m] : 0;
+    for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < n; x += (int64_t)gridDim.x * kThreads) {
+        K key = KeyOps<K>::zero();
+        bool bad = false;
+#pragma unroll
+        for (int m = 0; m < kMaxModes; m++) {
+            if (m >= N) break;
+            const uint32_t v = c.p[m][x];
+            bad |= (uint64_t)v >= dm[m];
+            const K *tm = lt + tab.eoff[m];
+            const int nb = tab.ebytes[m];
+            for (int j = 0; j < nb; j++) key_or(key, tm[j * 256 + (int)((v >> (8 * j)) & 0xffu)]);
+        }
+        if (bad) atomicOr(flag, 1);
+        keys[x] = key;
+    }
+}
+
 // ------------------------------------------------------------ radix sort
 // Stable LSD radix sort, 8-bit digits.  Each block owns one tile of
 // threads*ITEMS keys, split into one chunk of 64*ITEMS keys per wave;
@@ -649,9 +688,25 @@ unsigned grid_for(int64_t n, int per_block) {
 }  // namespace
 
 // ------------------------------------------------------------ launchers
-int launch_encode(int key_bits, const CoordPtrs &c, const uint64_t *dims, int64_t n, const RunTable &tab, void *keys,
-                  int *d_flag, hipStream_t s) {
+int launch_encode(int key_bits, const CoordPtrs &c, const uint64_t *dims, int64_t n, const RunTable &tab,
+                  const void *etab, void *keys, int *d_flag, hipStream_t s) {
     if (n <= 0) return ALTO_OK;
+    if (etab && tab.etab_entries > 0) {
+        const unsigned g = std::min<unsigned>(grid_for(n, kThreads * 4), 2048);
+        const size_t kb = key_bits / 8;
+        const size_t lds = (size_t)tab.etab_entries * kb;
+        if (lds > kEncodeTableMax) return set_error(ALTO_E_INVAL, "internal: deposit tables too large");
+        if (key_bits == 32)
+            encode_tab_k<uint32_t><<<g, kThreads, lds, s>>>(c, dims, n, tab, (const uint32_t *)etab, (uint32_t *)keys,
+                                                            d_flag);
+        else if (key_bits == 64)
+            encode_tab_k<uint64_t><<<g, kThreads, lds, s>>>(c, dims, n, tab, (const uint64_t *)etab, (uint64_t *)keys,
+                                                            d_flag);
+        else
+            encode_tab_k<u128><<<g, kThreads, lds, s>>>(c, dims, n, tab, (const u128 *)etab, (u128 *)keys, d_flag);
+        ALTO_HIP(hipGetLastError());
+        return ALTO_OK;
+    }
     const unsigned g = grid_for(n, kThreads * 4);
     if (key_bits == 32) encode_k<uint32_t><<<g, kThreads, 0, s>>>(c, dims, n, tab, (uint32_t *)keys, d_flag);
     else if (key_bits == 64) encode_k<uint64_t><<<g, kThreads, 0, s>>>(c, dims, n, tab, (uint64_t *)keys, d_flag);

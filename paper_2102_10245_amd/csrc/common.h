@@ -79,14 +79,23 @@ struct RunTable {
     uint32_t run[kMaxModes][kMaxRuns];
     // Compact form: mode n's coordinate is bits [coff[n], coff[n] + b_n) of
     // the word that the byte tables assemble (64 bits at most for indices of
-    // at most 64 bits; for 128-bit indices two 64-bit words, no coordinate
-    // straddling them, when the modes can be packed that way).
+    // at most 64 bits; for 128-bit indices a {lo, hi} pair of 64-bit words,
+    // which a coordinate may straddle).
     uint32_t coff[kMaxModes];
     uint32_t cmask[kMaxModes];
-    // 128-bit indices: index bytes covered by the byte tables (0: no tables,
-    // the bit runs above de-linearize)
+    // 128-bit indices: index bytes covered by the byte tables
     int tbytes128;
+    // Linearization by deposit tables: byte j of mode n's coordinate selects
+    // entry eoff[n] + 256 j + byte, which holds that byte's bits at their
+    // index positions (ebytes[n] = ceil(b_n / 8) bytes per coordinate).
+    // etab_entries = 0: no tables, the bit runs deposit.
+    uint32_t eoff[kMaxModes];
+    uint8_t ebytes[kMaxModes];
+    int etab_entries;
 };
+
+// largest deposit tables staged in LDS by the encode kernel
+constexpr size_t kEncodeTableMax = 64 * 1024;
 
 __device__ __forceinline__ int run_kpos(uint32_t r) { return (int)(r & 0xffu); }
 __device__ __forceinline__ int run_cpos(uint32_t r) { return (int)((r >> 8) & 0xffu); }
@@ -179,8 +188,10 @@ struct alto_tensor {
     alto::RunTable tab{};
     int64_t nnz_in = 0, nnz = 0;
     void *keys = nullptr;  // device, nnz * key_bits/8
-    void *ctab = nullptr;  // device byte tables of the compact form (key_bits <= 64)
+    void *ctab = nullptr;  // device byte tables of the compact form
     std::vector<uint8_t> h_ctab;  // their host image (source of the upload)
+    void *etab = nullptr;  // device deposit tables of the linearization
+    std::vector<uint8_t> h_etab;  // their host image
     float *vals = nullptr; // device, nnz
     double norm2 = 0.0;
     // the current partition, and recently used ones (so that alternating
@@ -212,7 +223,7 @@ int hip_error(hipError_t e, const char *what);
 // ---------------------------------------------------------------- launchers
 // build.hip
 int launch_encode(int key_bits, const CoordPtrs &c, const uint64_t *dims, int64_t n, const RunTable &tab,
-                  void *keys, int *d_flag, hipStream_t s);
+                  const void *etab, void *keys, int *d_flag, hipStream_t s);
 int radix_sort(int key_bits, int nbits, int64_t n, void *keys, float *vals, void *keys_alt, float *vals_alt,
                void *scratch, size_t scratch_bytes, bool *result_in_alt, hipStream_t s);
 size_t radix_sort_scratch(int key_bits, int64_t n);

@@ -21,6 +21,9 @@ CASES = [
     (synth.Recipe("order2", (5000, 3000), 40_000, (1.0, 0), seed=5), 0, 64),
     (synth.Recipe("order6", (40, 30, 20, 10, 7, 3), 60_000, (0.5,) * 6, seed=6), 0, 333),
     (synth.Recipe("order8", (9, 8, 7, 6, 5, 4, 3, 2), 30_000, (), seed=7), 0, 40),
+    # 120-bit index whose deposit tables (18 coordinate bytes x 256 x 16 B)
+    # exceed the LDS budget of the table encoder: the bit-run encoder runs
+    (synth.Recipe("order6_wide", (1 << 20,) * 6, 50_000, (0.7, 0, 0, 0, 0, 0), seed=8), 0, 128),
 ]
 
 
