@@ -165,8 +165,9 @@ int alto_mttkrp(alto_tensor *t, const void *const *factors, int R, int prec, int
 /*
  * cp_als — `iters` iterations of CP-ALS (Section 2.2): for each mode n in
  * turn, M_n = MTTKRP_n; V = Hadamard product of the Grams A_m^T A_m, m != n
- * (FP64); A_n = M_n V^{-1} through the Cholesky factor of V (one retry with
- * a ridge of 1e-10*trace(V)/R); lambda = column 2-norms; A_n /= lambda;
+ * (FP64); A_n = M_n V^{-1}, V inverted by Gauss-Jordan elimination whose
+ * pivots must stay positive (the Cholesky criterion; one retry with a ridge
+ * of 1e-10*trace(V)/R); lambda = column 2-norms; A_n /= lambda;
  * then the Gram of the stored A_n.  After the last mode of each iteration:
  * fit = 1 - ||X - [[lambda; A_1..A_N]]|| / ||X||.
  *   factors  host array of N device pointers, I_n x R in precision `prec`:
@@ -187,7 +188,11 @@ int cp_als(alto_tensor *t, int R, int iters, int prec, void *const *factors, dou
  *   - no selector weights loaded: the reuse rule of Section 3.3 (staged if
  *     nnz / I_mode > 4, atomic otherwise) with the current L;
  *   - weights loaded, tensor inside the range the network was trained on:
- *     the network's choice;
+ *     the network's choice; with the environment variable
+ *     ALTO_SELECT_MARGIN = m > 0 (log2 time, default 0), when other
+ *     candidates are predicted within m of that choice, the fastest of the
+ *     (at most three) closest ones found by timing them, on the same terms
+ *     as below;
  *   - weights loaded, tensor outside that range: the fastest candidate found
  *     by timing every (strategy, L) the network chooses among.  An AUTO
  *     alto_mttkrp or cp_als does that timing on first use of (mode, R, prec)

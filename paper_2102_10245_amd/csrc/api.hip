@@ -351,8 +351,7 @@ int ensure_workspace(alto_tensor *t, size_t bytes) {
 // plan and order, time a second run with events on the stream, keep the
 // fastest.  The selector's fallback outside its training range.
 int autotune(alto_tensor *t, const void *const *factors, int R, int prec, int mode, float *out, hipStream_t s,
-             alto_exec *best) {
-    const std::vector<alto_exec> cands = selector_candidates();
+             const std::vector<alto_exec> &cands, alto_exec *best) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     ALTO_HIP(hipEventCreate(&e0));
     hipError_t he = hipEventCreate(&e1);
@@ -392,15 +391,19 @@ int resolve_strategy(alto_tensor *t, const void *const *factors, int R, int prec
         return ALTO_OK;
     }
     alto_exec sel;
-    const int src = select_plan(t, mode, R, prec, &sel);
+    std::vector<alto_exec> close;
+    const int src = select_plan(t, mode, R, prec, &sel, &close);
     if (ex && ex->num_segments > 0) {
         sel.num_segments = ex->num_segments;  // a fixed L: the strategy as chosen
-    } else if (src == kPlanOutside && t->nnz > 0) {
+    } else if ((src == kPlanOutside || src == kPlanClose) && t->nnz > 0) {
+        // time every candidate (outside the training range) or the close
+        // ones, once per (mode, R, prec); the tensor keeps the fastest
         const uint64_t key = tuned_key(mode, R, prec);
         auto it = t->tuned.find(key);
         if (it == t->tuned.end()) {
             alto_exec best{};
-            const int rc = autotune(t, factors, R, prec, mode, out, s, &best);
+            const int rc = autotune(t, factors, R, prec, mode, out, s,
+                                    src == kPlanClose ? close : selector_candidates(), &best);
             if (rc) return rc;
             it = t->tuned.emplace(key, best).first;
         }

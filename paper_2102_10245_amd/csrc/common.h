@@ -259,9 +259,12 @@ int mlp_adam(int64_t P, float *params, const float *grads, float *m, float *v, f
              float eps, int t, hipStream_t s);
 
 // selector.hip: where an automatic plan comes from
-enum { kPlanRule = 0, kPlanNet = 1, kPlanOutside = 2 };
-// the selector's (or, without weights, the reuse rule's) plan and its source
-int select_plan(const alto_tensor *t, int mode, int R, int prec, alto_exec *out);
+enum { kPlanRule = 0, kPlanNet = 1, kPlanOutside = 2, kPlanClose = 3 };
+// the selector's (or, without weights, the reuse rule's) plan and its
+// source; kPlanClose: the network's best prediction is within the margin
+// (ALTO_SELECT_MARGIN, log2 time) of others, listed in *close (best first)
+int select_plan(const alto_tensor *t, int mode, int R, int prec, alto_exec *out,
+                std::vector<alto_exec> *close = nullptr);
 // every (strategy, L) the selector chooses among
 std::vector<alto_exec> selector_candidates();
 inline uint64_t tuned_key(int mode, int R, int prec) {

@@ -6,7 +6,9 @@
 // Inference here is on the host: one query is ~6K multiply-adds, far
 // cheaper than a kernel launch and a device-to-host copy; the HIP kernels
 // in mlp.hip run the same network in batch for training and evaluation.
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <mutex>
 #include <vector>
 
@@ -59,8 +61,20 @@ void heuristic(const alto_tensor *t, int mode, alto_exec *out) {
     out->num_segments = 0;
 }
 
+// candidates timed at most when the network's predictions are close
+constexpr int kCloseMax = 3;
+
+// margin of predicted log2 time under which the network's runners-up are
+// timed too (ALTO_SELECT_MARGIN; 0, the default, trusts the argmin)
+float close_margin() {
+    const char *e = getenv("ALTO_SELECT_MARGIN");
+    const float m = e && *e ? (float)atof(e) : 0.f;
+    return m > 0.f ? m : 0.f;
+}
+
 // The plan of (tensor, mode, R, prec) and where it came from.
-int select_impl(const alto_tensor *t, int mode, int R, int prec, alto_exec *out) {
+int select_impl(const alto_tensor *t, int mode, int R, int prec, alto_exec *out,
+                std::vector<alto_exec> *close = nullptr) {
     std::lock_guard<std::mutex> lk(g_sel_mu);
     if (!g_sel.loaded || t->nnz == 0) {
         heuristic(t, mode, out);
@@ -88,25 +102,39 @@ int select_impl(const alto_tensor *t, int mode, int R, int prec, alto_exec *out)
         for (int q = 0; q < s.H; q++) a += s.W2[(size_t)j * s.H + q] * h1[q];
         h2[j] = a > 0.f ? a : 0.f;
     }
+    std::vector<float> y(s.K);
     int best = 0;
-    float best_y = INFINITY;
     for (int k = 0; k < s.K; k++) {
         float a = s.b3[k];
         for (int q = 0; q < s.H; q++) a += s.W3[(size_t)k * s.H + q] * h2[q];
-        if (a < best_y) {
-            best_y = a;
-            best = k;
+        y[k] = a;
+        if (a < y[best]) best = k;
+    }
+    auto plan = [&](int k) { return alto_exec{kOrder[k / s.nL], (int)s.Ls[k % s.nL]}; };
+    *out = plan(best);
+    const float margin = close_margin();
+    if (margin > 0.f) {
+        // candidates predicted within the margin of the best, best first
+        std::vector<int> ks;
+        for (int k = 0; k < s.K; k++)
+            if (y[k] <= y[best] + margin) ks.push_back(k);
+        std::stable_sort(ks.begin(), ks.end(), [&](int a, int b) { return y[a] < y[b]; });
+        if (ks.size() > (size_t)kCloseMax) ks.resize(kCloseMax);
+        if (ks.size() > 1) {
+            if (close) {
+                close->clear();
+                for (int k : ks) close->push_back(plan(k));
+            }
+            return kPlanClose;
         }
     }
-    out->strategy = kOrder[best / s.nL];
-    out->num_segments = (int)s.Ls[best % s.nL];
     return kPlanNet;
 }
 
 }  // namespace
 
-int select_plan(const alto_tensor *t, int mode, int R, int prec, alto_exec *out) {
-    return select_impl(t, mode, R, prec, out);
+int select_plan(const alto_tensor *t, int mode, int R, int prec, alto_exec *out, std::vector<alto_exec> *close) {
+    return select_impl(t, mode, R, prec, out, close);
 }
 
 std::vector<alto_exec> selector_candidates() {
@@ -179,8 +207,10 @@ int alto_select(const alto_tensor *t, int mode, int R, int prec, alto_exec *out)
     if (!t || !out) return set_error(ALTO_E_INVAL, "null argument");
     if (mode < 0 || mode >= t->N) return set_error(ALTO_E_INVAL, "mode out of range");
     if (R < 1 || R > ALTO_MAX_RANK) return set_error(ALTO_E_INVAL, "R must be in 1..256");
-    if (select_impl(t, mode, R, prec, out) == kPlanOutside) {
-        // outside the training range: the plan found by timing, once there is one
+    const int src = select_impl(t, mode, R, prec, out);
+    if (src == kPlanOutside || src == kPlanClose) {
+        // outside the training range, or close predictions: the plan found by
+        // timing, once there is one
         const auto it = t->tuned.find(tuned_key(mode, R, prec));
         if (it != t->tuned.end()) *out = it->second;
     }

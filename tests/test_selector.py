@@ -188,3 +188,53 @@ def test_outside_training_range_times_every_candidate():
     finally:
         alto.selector_load(None)
         t.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.skipif(not _gpu(), reason="needs a GPU")
+def test_close_predictions_time_the_closest_candidates(monkeypatch):
+    """Inside the training range, with ALTO_SELECT_MARGIN set so wide that
+    every candidate counts as close: alto_select reports the network's argmin
+    until an AUTO MTTKRP has timed the three best-predicted candidates, then
+    the fastest of them; the AUTO result matches the oracle.  Without the
+    margin the argmin stands and nothing is timed."""
+    import torch
+    import synth
+    from gpu_common import rel_fro
+    rec = synth.Recipe("inside_range", (20_000, 5_000, 3_000), 1_500_000, (0.8, 0.5, 0), seed=33)
+    coords, vals = synth.coo(rec)
+    c = torch.from_numpy(coords.view(np.int32)).cuda()
+    v = torch.from_numpy(vals).cuda()
+    t = alto.AltoTensor.build(c, v, rec.dims)
+    R = 16
+    w = _weights()
+    mlp = oracle.MLP(*w["params"])
+    try:
+        assert alto.load_default_selector()
+        fs = synth.factors(rec.seed + 1, rec.dims, R)
+        fd = [torch.from_numpy(f).cuda() for f in fs]
+        for mode in range(3):
+            monkeypatch.delenv("ALTO_SELECT_MARGIN", raising=False)
+            x = t.selector_features(mode, R, "f32").astype(np.float64)
+            assert np.all(x >= w["fmin"] - 0.25 * (w["fmax"] - w["fmin"]) - 0.5)
+            assert np.all(x <= w["fmax"] + 0.25 * (w["fmax"] - w["fmin"]) + 0.5)
+            y, _ = mlp.forward(((x - w["mean"]) / w["scale"])[None, :])
+            order = np.argsort(y[0], kind="stable")
+            argmin = t.select(mode, R, "f32")
+            assert argmin[1] > 0  # the network's plan, not the reuse rule
+            # the three best-predicted candidates (a fourth one tied with the
+            # third within float noise is accepted too)
+            allowed = {st.candidate(k) for k in order[:3]}
+            if y[0][order[3]] - y[0][order[2]] < 1e-4:
+                allowed.add(st.candidate(order[3]))
+            monkeypatch.setenv("ALTO_SELECT_MARGIN", "100")
+            assert t.select(mode, R, "f32") == argmin  # nothing timed yet
+            out = t.mttkrp(fd, mode, strategy="auto").cpu().numpy()
+            kept = t.select(mode, R, "f32")
+            assert kept in allowed, (kept, allowed)
+            assert t.select(mode, R, "f32") == kept
+            ref = oracle.mttkrp(rec.dims, coords, vals, fs, mode)
+            assert rel_fro(out, ref) <= 1e-5
+    finally:
+        alto.selector_load(None)
+        t.close()
