@@ -13,6 +13,7 @@ Storage of Sparse Tensors" (Helal et al., ICS 2021):
                                    mode intervals T_{l,n})
   coverage ....................... Algorithm 2, pull-based accumulation
   mttkrp, mttkrp_rows ............ Section 2.2 and Algorithm 1
+  mttkrp_par ..................... the same sum on every host core (timing)
   cp_als ......................... Section 2.2 (CPD-ALS; standard ALS)
   heuristic_staging .............. Section 3.3 (reuse > 4 memory operations)
   storage_bits / ratio ........... Eq. 1 and Eq. 2
@@ -42,7 +43,7 @@ def build(force: bool = True) -> str:
     """Compile oracle.c with gcc into liboracle.so."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-std=gnu11", _SRC, "-o", tmp, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=gnu11", _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -66,6 +67,8 @@ def _load():
         L.oracle_intervals.argtypes = [c_int, c_int, vp, vp, vp, vp, vp, vp]
         L.oracle_coverage.argtypes = [c_int, c_int, vp, c_int, ctypes.c_uint64, vp]
         L.oracle_mttkrp.argtypes = [c_int, i64, vp, vp, vp, vp, c_int, c_int, vp]
+        L.oracle_mttkrp_par.argtypes = [c_int, i64, vp, vp, vp, vp, c_int, c_int, vp]
+        L.oracle_mttkrp_par.restype = c_int
         L.oracle_mttkrp_rows.argtypes = [c_int, i64, vp, vp, vp, vp, c_int, c_int, i64, vp, vp]
         L.oracle_mttkrp_rows.restype = c_int
         L.oracle_norm2.argtypes = [c_int, i64, vp, vp]
@@ -214,6 +217,22 @@ def mttkrp(dims, coords, vals, factors, mode: int):
     _load().oracle_mttkrp(len(dims), v.shape[0], _ptrs(rows), v.ctypes.data, d.ctypes.data,
                           _ptrs(fs), R, mode, out.ctypes.data)
     return out
+
+
+def mttkrp_par(dims, coords, vals, factors, mode: int):
+    """The same MTTKRP on every host core (OpenMP, thread-private outputs
+    added at the end).  Returns (out, threads used)."""
+    rows = _u32_rows(coords)
+    v = np.ascontiguousarray(vals, np.float64)
+    fs = _f64_rows(factors)
+    R = fs[0].shape[1]
+    d = np.array(dims, np.uint64)
+    out = np.zeros((int(dims[mode]), R), np.float64)
+    used = _load().oracle_mttkrp_par(len(dims), v.shape[0], _ptrs(rows), v.ctypes.data, d.ctypes.data,
+                                     _ptrs(fs), R, mode, out.ctypes.data)
+    if used < 0:
+        raise MemoryError
+    return out, used
 
 
 def mttkrp_rows(dims, coords, vals, factors, mode: int, rows_sel):

@@ -23,6 +23,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_MAXN 16
 
@@ -270,6 +273,53 @@ void oracle_mttkrp(int N, int64_t M, const uint32_t *const *coords, const double
     }
 }
 
+/* The same definition spread over the host's cores with OpenMP: thread t
+ * sums a contiguous share of the nonzeros into an output of its own, and
+ * those outputs are added in thread order at the end, so only the order of
+ * the floating-point sums differs from oracle_mttkrp.  It exists to time
+ * the oracle on every core.  Returns the number of threads used, or -1 if
+ * the private outputs cannot be allocated. */
+int oracle_mttkrp_par(int N, int64_t M, const uint32_t *const *coords, const double *vals,
+                      const uint64_t *dims, const double *const *factors, int R, int mode,
+                      double *out)
+{
+    const size_t n_out = (size_t)dims[mode] * (size_t)R;
+    int nt = 1;
+#ifdef _OPENMP
+    nt = omp_get_max_threads();
+#endif
+    double *priv = (double *)calloc((size_t)nt * n_out, sizeof(double));
+    if (!priv) return -1;
+    int used = 1;
+#pragma omp parallel num_threads(nt)
+    {
+        int t = 0, T = 1;
+#ifdef _OPENMP
+        t = omp_get_thread_num();
+        T = omp_get_num_threads();
+#endif
+        if (t == 0) used = T;
+        double *mine = priv + (size_t)t * n_out;
+        const int64_t x0 = M * t / T, x1 = M * (t + 1) / T;
+        for (int64_t x = x0; x < x1; x++) {
+            double *o = mine + (size_t)coords[mode][x] * (size_t)R;
+            for (int r = 0; r < R; r++) {
+                double p = vals[x];
+                for (int m = 0; m < N; m++) {
+                    if (m == mode) continue;
+                    p *= factors[m][(size_t)coords[m][x] * (size_t)R + (size_t)r];
+                }
+                o[r] += p;
+            }
+        }
+    }
+    memset(out, 0, n_out * sizeof(double));
+    for (int t = 0; t < used; t++)
+        for (size_t q = 0; q < n_out; q++) out[q] += priv[(size_t)t * n_out + q];
+    free(priv);
+    return used;
+}
+
 /* Same definition restricted to a list of output rows (for checks at
  * sizes where the full dense output is not needed).  rows[] are distinct.
  * out is nrows x R. */
@@ -361,15 +411,15 @@ double oracle_norm2(int N, int64_t M, const uint32_t *const *coords, const doubl
     return s;
 }
 
-/* Gram G = A^T A (R x R) of an I x R matrix. */
+/* Gram G = A^T A (R x R) of an I x R matrix.  Every entry is the sum over
+ * rows i = 0, 1, ..., I-1 in that order (rows in the outer loop only so the
+ * matrix is read row by row). */
 static void or_gram(uint64_t I, int R, const double *A, double *G)
 {
-    for (int a = 0; a < R; a++)
-        for (int b = 0; b < R; b++) {
-            double s = 0.0;
-            for (uint64_t i = 0; i < I; i++) s += A[i * R + a] * A[i * R + b];
-            G[a * R + b] = s;
-        }
+    for (int q = 0; q < R * R; q++) G[q] = 0.0;
+    for (uint64_t i = 0; i < I; i++)
+        for (int a = 0; a < R; a++)
+            for (int b = 0; b < R; b++) G[a * R + b] += A[i * R + a] * A[i * R + b];
 }
 
 /* factors: N pointers to I_n x R FP64 matrices (in: initial guess; out:
@@ -430,13 +480,14 @@ int oracle_cp_als(int N, int64_t M, const uint32_t *const *coords, const double 
             }
             free(Vc);
             /* lambda = column 2-norms; normalize the columns */
-            for (int r = 0; r < R; r++) {
-                double s = 0.0;
-                for (uint64_t i = 0; i < I; i++) s += A[i * R + r] * A[i * R + r];
-                lambda[r] = sqrt(s);
-                if (lambda[r] > 0.0)
-                    for (uint64_t i = 0; i < I; i++) A[i * R + r] /= lambda[r];
-            }
+            /* (column sums over i = 0..I-1 in order, rows in the outer loop) */
+            for (int r = 0; r < R; r++) y[r] = 0.0;
+            for (uint64_t i = 0; i < I; i++)
+                for (int r = 0; r < R; r++) y[r] += A[i * R + r] * A[i * R + r];
+            for (int r = 0; r < R; r++) lambda[r] = sqrt(y[r]);
+            for (uint64_t i = 0; i < I; i++)
+                for (int r = 0; r < R; r++)
+                    if (lambda[r] > 0.0) A[i * R + r] /= lambda[r];
             or_gram(I, R, A, G + (size_t)n * R * R);
         }
         /* fit after the last mode:  ||X - Xhat||^2 = ||X||^2 + ||Xhat||^2 - 2<X,Xhat> */

@@ -317,6 +317,22 @@ def test_mttkrp_linearity_and_order_invariance():
     assert np.allclose(oracle.mttkrp(dims, c[:, p], v1[p], fs, 2), a, rtol=1e-12)
 
 
+def test_mttkrp_par_matches_serial():
+    """The all-core variant differs from the serial loop only in the order of
+    the sums (thread-private outputs added at the end)."""
+    rng = np.random.default_rng(19)
+    dims = (300, 200, 100, 7)
+    M = 50_000
+    c = np.stack([rng.integers(0, d, M) for d in dims]).astype(np.uint32)
+    v = rng.standard_normal(M)
+    fs = [rng.standard_normal((d, 5)) for d in dims]
+    for mode in range(4):
+        ref = oracle.mttkrp(dims, c, v, fs, mode)
+        got, used = oracle.mttkrp_par(dims, c, v, fs, mode)
+        assert used >= 1
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
 def test_mttkrp_rows_subset():
     rng = np.random.default_rng(14)
     dims = (100, 30, 10)
@@ -411,6 +427,71 @@ def test_cp_als_unit_columns():
     fs, lam, _ = oracle.cp_als(dims, c, rng.random(200), [rng.random((d, 3)) for d in dims], 3)
     for f in fs:
         assert np.allclose(np.linalg.norm(f, axis=0), 1.0, rtol=1e-12)
+
+
+def _als_sweep_with_ridge(dims, X, init, eps):
+    """One ALS sweep in NumPy from the dense tensor X, adding the ridge
+    eps * trace(V) / R to the diagonal of V whenever V has no Cholesky
+    factor.  Returns (factors, lambda, number of ridged updates)."""
+    fs = [np.array(f, np.float64) for f in init]
+    R = fs[0].shape[1]
+    lam = np.ones(R)
+    ridged = 0
+    for n in range(len(dims)):
+        Xn = np.moveaxis(X, n, 0).reshape(dims[n], -1)
+        KR = np.ones((1, R))
+        for m in range(len(dims)):
+            if m != n:
+                KR = (KR[:, None, :] * fs[m][None, :, :]).reshape(-1, R)
+        Mn = Xn @ KR
+        V = np.ones((R, R))
+        for m in range(len(dims)):
+            if m != n:
+                V *= fs[m].T @ fs[m]
+        try:
+            np.linalg.cholesky(V)
+        except np.linalg.LinAlgError:
+            V = V + eps * np.trace(V) / R * np.eye(R)
+            ridged += 1
+        A = np.linalg.solve(V, Mn.T).T
+        lam = np.linalg.norm(A, axis=0)
+        A[:, lam > 0] /= lam[lam > 0]
+        fs[n] = A
+    return fs, lam, ridged
+
+
+def test_cp_als_ridge_retry():
+    """A singular normal-equation matrix takes the ridge reading (one retry
+    with 1e-10 * trace(V) / R on the diagonal).  Column 3 is zero in modes 1
+    and 2, so every V of the sweep has a zero row; columns 1 and 2 are nearly
+    parallel in every mode, so V is ill-conditioned on the rest and the size
+    of the ridge shows in the solution (a scale off by 2x, or the trace not
+    divided by R, moves it far beyond the tolerance)."""
+    rng = np.random.default_rng(31)
+    dims = (12, 10, 8)
+    R = 4
+    X = rng.random(dims)
+    c = np.stack(np.nonzero(np.ones(dims))).astype(np.uint32)
+    v = X[tuple(c)]
+    init = [rng.random((d, R)) for d in dims]
+    for f in init:
+        f[:, 2] = f[:, 1] + 1e-4 * rng.standard_normal(f.shape[0])
+    init[1][:, 3] = 0.0
+    init[2][:, 3] = 0.0
+    fs, lam, _ = oracle.cp_als(dims, c, v, init, 1)
+    ref, rlam, ridged = _als_sweep_with_ridge(dims, X, init, 1e-10)
+    assert ridged == 3  # every update needed the ridge
+    err = max(np.abs(a - b).max() for a, b in zip(fs, ref))
+    assert err <= 1e-9, err
+    assert np.allclose(lam, rlam, rtol=1e-7)
+    assert np.all(fs[1][:, 3] == 0.0) and np.all(fs[2][:, 3] == 0.0)
+    # the test can tell a wrong ridge from the right one
+    for wrong in (2e-10, 5e-11, 4e-10):
+        alt, _, _ = _als_sweep_with_ridge(dims, X, init, wrong)
+        assert max(np.abs(a - b).max() for a, b in zip(fs, alt)) > 1e3 * 1e-9, wrong
+    # no retry beyond the one: zero factors keep V zero even with the ridge
+    with pytest.raises(np.linalg.LinAlgError):
+        oracle.cp_als(dims, c, v, [np.zeros((d, R)) for d in dims], 1)
 
 
 # ------------------------------------------------------------ BF16
