@@ -17,6 +17,8 @@ Storage of Sparse Tensors" (Helal et al., ICS 2021):
   cp_als ......................... Section 2.2 (CPD-ALS; standard ALS)
   heuristic_staging .............. Section 3.3 (reuse > 4 memory operations)
   storage_bits / ratio ........... Eq. 1 and Eq. 2
+  transpose ...................... sparse tensor transposition (the sparse
+                                   tensor operations of the related work)
   bf16_round ..................... storage rule for bfloat16 factors
   mlp_forward / mlp_backward ..... selector network (two hidden layers)
 """
@@ -271,6 +273,28 @@ def cp_als(dims, coords, vals, init_factors, iters: int):
     if rc:
         raise MemoryError
     return fs, lam, fit
+
+
+# ---------------------------------------------------------------- transposition
+def transpose(coords, vals, perm):
+    """The nonzeros of a COO tensor (repeated coordinates summed in FP64, in
+    input order) listed in lexicographic order of their coordinates taken in
+    the mode order perm[0], perm[1], ... (perm[0] most significant).
+    Returns (coords uint32 [N, M'] with row j the coordinates along mode
+    perm[j], vals float64 [M'])."""
+    c = np.asarray(coords, np.uint32)
+    v = np.asarray(vals, np.float64)
+    N = c.shape[0]
+    pc = c[list(perm)]
+    if c.shape[1] == 0:
+        return pc, v
+    # np.lexsort sorts by its last key first: pass the least significant first
+    order = np.lexsort(tuple(pc[j] for j in range(N - 1, -1, -1)))
+    pc, v = pc[:, order], v[order]
+    new = np.ones(pc.shape[1], bool)
+    new[1:] = np.any(pc[:, 1:] != pc[:, :-1], axis=0)
+    starts = np.nonzero(new)[0]
+    return np.ascontiguousarray(pc[:, starts]), np.add.reduceat(v, starts)
 
 
 # ---------------------------------------------------------------- misc

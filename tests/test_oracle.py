@@ -494,7 +494,25 @@ def test_cp_als_ridge_retry():
         oracle.cp_als(dims, c, v, [np.zeros((d, R)) for d in dims], 1)
 
 
-# ------------------------------------------------------------ BF16
+@pytest.mark.parametrize("dims,perm", [((4, 8, 2), (1, 0, 2)), ((5, 3, 4, 2), (3, 1, 0, 2)),
+                                       ((6, 7), (1, 0)), ((3, 4, 5), (0, 1, 2))])
+def test_transpose_matches_dense_transpose(dims, perm):
+    """Transposition: the nonzeros of np.transpose(X, perm) in row-major
+    (C) order are exactly the lexicographic order of the permuted coordinates;
+    repeated COO entries are summed."""
+    rng = np.random.default_rng(41)
+    M = 40
+    c = np.stack([rng.integers(0, d, M) for d in dims]).astype(np.uint32)
+    v = rng.random(M) + 0.5
+    X = _dense(dims, c, v)
+    Y = np.transpose(X, perm)
+    ref_idx = np.nonzero(Y)
+    got_c, got_v = oracle.transpose(c, v, perm)
+    assert all(np.array_equal(got_c[j], ref_idx[j]) for j in range(len(dims)))
+    assert np.allclose(got_v, Y[ref_idx], rtol=1e-15)
+
+
+# ------------------------------------------------------------ BF16# ------------------------------------------------------------ BF16
 def test_bf16_matches_torch_rne():
     torch = pytest.importorskip("torch")
     rng = np.random.default_rng(31)
