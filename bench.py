@@ -11,10 +11,14 @@ value = MTTKRP nonzeros processed per second over the whole step
         (iterations x modes x distinct nonzeros / step time).
 
 Extra fields: per-mode MTTKRP time, nnz/s and % of the 8 TB/s HBM peak in
-algorithmic bytes for every strategy, FP32 and BF16 factors; CP-ALS ms per
-iteration and fit for the plain FP32 form (reuse rule, no network) and the
-network-chosen FP32 and BF16 forms; `roofline` for the MTTKRP kernel;
-`cpu_baseline` (the FP64 oracle on a bounded sample, one host core).
+compulsory bytes (each nonzero's index and value, each factor row and each
+output row moved once) for every strategy, FP32 and BF16 factors; CP-ALS ms
+per iteration and fit for the plain FP32 form (reuse rule, no network), the
+network-chosen FP32 and BF16 forms and FP32 / BF16 under one fixed plan;
+`roofline` for the MTTKRP kernel (compulsory bytes over the mean launch
+time, with the counter-measured HBM traffic beside it); `cpu_baseline` (the
+FP64 oracle on a bounded sample, all host cores and one core); the
+alto_build time and the device memory the tensor handle holds.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -57,6 +61,15 @@ def logical_bytes_per_nnz(N, R, key_bits, fbytes):
     """Algorithmic bytes one nonzero moves in a mode-n MTTKRP: its index and
     value, N-1 gathered factor rows, and its R-wide FP32 output update."""
     return key_bits / 8 + 4 + (N - 1) * R * fbytes + 4 * R
+
+
+def compulsory_bytes(info, R, fbytes, mode):
+    """The least HBM traffic a mode-n MTTKRP can have: every nonzero's index
+    and value read once, every factor row of the other modes read once, and
+    every output row written once."""
+    dims = info["dims"]
+    return (info["nnz"] * (info["key_bits"] / 8 + 4)
+            + sum(d * R * fbytes for m, d in enumerate(dims) if m != mode) + dims[mode] * R * 4)
 
 
 def format_experiment(alto, torch, synth, dev, reps=3):
@@ -133,7 +146,7 @@ def main():
     N = len(rec.dims)
     torch.cuda.synchronize()
 
-    def step(prec="f32", timers=None):
+    def step(prec="f32", timers=None, strategy="auto", num_segments=0):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)] if timers is not None else None
         for w, s in zip(work[prec], src[prec]):
             w.copy_(s)
@@ -142,11 +155,12 @@ def main():
         t = alto.AltoTensor.build(c_dev, v_dev, rec.dims)
         if ev:
             ev[1].record()
-        lam, fit = t.cp_als(work[prec], args.iters)
+        lam, fit = t.cp_als(work[prec], args.iters, strategy=strategy, num_segments=num_segments)
         if ev:
             ev[2].record()
         info = t.info()
-        plan = [t.select(m, R, prec) for m in range(N)]
+        plan = ([t.select(m, R, prec) for m in range(N)] if strategy == "auto"
+                else [(strategy, num_segments or info["num_segments"])] * N)
         t.close()
         if timers is not None:
             torch.cuda.synchronize()
@@ -184,19 +198,25 @@ def main():
     ms_per_step = 1e3 * elapsed / args.steps
     value = args.iters * N * M / (elapsed / args.steps)
 
-    # the forms: network-chosen FP32 / BF16, and the plain FP32 form (reuse rule)
+    # the forms: network-chosen FP32 / BF16, the plain FP32 form (reuse rule,
+    # no network), and FP32 / BF16 under one fixed plan (sorted, L = 512)
     forms = {}
-    for name, prec, sel in (("selector_f32", "f32", have_sel), ("selector_bf16", "bf16", have_sel),
-                            ("plain_f32", "f32", False)):
+    for name, prec, sel, st, L in (("selector_f32", "f32", have_sel, "auto", 0),
+                                   ("selector_bf16", "bf16", have_sel, "auto", 0),
+                                   ("plain_f32", "f32", False, "auto", 0),
+                                   ("fixed_sorted512_f32", "f32", have_sel, "sorted", 512),
+                                   ("fixed_sorted512_bf16", "bf16", have_sel, "sorted", 512)):
         if not sel:
             alto.selector_load(None)
         tim = []
-        _, fit, plan = step(prec, tim)
+        finfo, fit, plan = step(prec, tim, st, L)
         if have_sel:
             alto.load_default_selector()
         forms[name] = {"build_ms": tim[0][0], "cp_als_ms_per_iter": tim[0][1] / args.iters,
                        "fit": float(fit[-1]) if len(fit) else None,
-                       "plan": [{"strategy": s, "num_segments": L} for s, L in plan]}
+                       "plan": [{"strategy": s, "num_segments": L} for s, L in plan],
+                       "device_bytes": {k: finfo[k] for k in ("tensor_bytes", "partition_bytes", "order_bytes",
+                                                              "scratch_bytes")}}
         log(f"{name}: CP-ALS {tim[0][1] / args.iters:.2f} ms/iter, fit {forms[name]['fit']:.6f}, plan {plan}")
 
     # per-mode MTTKRP for every strategy and precision on the built tensor
@@ -208,15 +228,23 @@ def main():
     kb = t.info()["key_bits"]
     t.close()
 
-    # roofline of the MTTKRP kernel under the chosen FP32 plan: algorithmic
-    # bytes per launch over the mean launch time (all modes pooled)
+    # roofline of the MTTKRP kernel under the chosen FP32 plan: compulsory
+    # HBM bytes per launch over the mean launch time (all modes pooled)
     main_modes = per_mode["auto_f32"]
-    tot_bytes = sum(m["logical_bytes"] for m in main_modes)
+    tot_bytes = sum(m["compulsory_bytes"] for m in main_modes)
+    tot_logical = sum(m["logical_bytes"] for m in main_modes)
     tot_ms = sum(m["ms"] for m in main_modes)
     achieved = tot_bytes / (tot_ms * 1e-3) / 1e9
+    traffic = measured_traffic(rec.name)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(rec.name),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "bytes": "compulsory: nnz*(W/8+4) + sum over other modes I_m*R*4 + I_n*R*4 per launch",
+                "compulsory_bytes_per_launch": round(tot_bytes / N),
+                "mean_launch_ms": tot_ms / N,
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
+                "traffic_frac": (round(traffic / (tot_ms / N * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                                 if traffic else None),
+                "logical_GBps": round(tot_logical / (tot_ms * 1e-3) / 1e9, 1),
                 "kernel": "mttkrp_k (64-bit index, order 4, R=32, FP32 factors), mean over the 4 modes"}
 
     cpu = None
@@ -245,6 +273,9 @@ def main():
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "build_ms": forms["selector_f32"]["build_ms"],
+        "footprint": {**forms["selector_f32"]["device_bytes"], "coo_input_bytes": rec.nnz * (4 * N + 4),
+                      "note": "device bytes the tensor handle holds after the FP32 CP-ALS of one step"},
         "forms": forms,
         "per_mode": per_mode,
         "fit_f32": float(fit_f32[-1]) if len(fit_f32) else None,
@@ -289,33 +320,59 @@ def time_modes(alto, torch, t, factors, R, N, reps, prec, strategy):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
         lb = logical_bytes_per_nnz(N, R, info["key_bits"], fb) * M
+        cb = compulsory_bytes(info, R, fb, mode)
         res.append({"mode": mode, "strategy": strat, "num_segments": L or info["num_segments"], "ms": ms,
-                    "nnz_per_s": M / (ms * 1e-3), "logical_bytes": lb, "logical_GBps": lb / (ms * 1e-3) / 1e9,
-                    "pct_hbm_peak": 100.0 * lb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS})
+                    "nnz_per_s": M / (ms * 1e-3), "compulsory_bytes": cb,
+                    "pct_hbm_peak": 100.0 * cb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "logical_bytes": lb, "logical_GBps": lb / (ms * 1e-3) / 1e9})
         log(f"mode {mode} {prec} {strategy}->{strat}: {ms:.3f} ms, {M / (ms * 1e-3) / 1e9:.2f} G nnz/s, "
-            f"{res[-1]['pct_hbm_peak']:.1f}% of HBM peak (algorithmic bytes)")
+            f"{res[-1]['pct_hbm_peak']:.1f}% of HBM peak (compulsory bytes)")
     return res
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(rec, coords, vals, init, R, N, seconds):
-    """The FP64 oracle's COO MTTKRP (one host core) on the first S draws of
-    the same tensor, all modes; S sized for about `seconds` of work."""
+    """The FP64 oracle's COO MTTKRP on the first S draws of the same tensor,
+    all modes: on every host core (OpenMP, thread-private outputs added at
+    the end) and on one core, each leg sized for about `seconds` of work."""
     import oracle
     oracle.build(force=False)
     init = [np.asarray(f, np.float64) for f in init]
-    s = 200000
-    t0 = time.perf_counter()
-    for mode in range(N):
-        oracle.mttkrp(rec.dims, coords[:, :s], vals[:s], init, mode)
-    dt = time.perf_counter() - t0
-    s = int(min(coords.shape[1], max(s, s * seconds / max(dt, 1e-9))))
-    t0 = time.perf_counter()
-    for mode in range(N):
-        oracle.mttkrp(rec.dims, coords[:, :s], vals[:s], init, mode)
-    dt = time.perf_counter() - t0
-    return {"value": s * N / dt, "unit": "nnz/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {s} COO draws of {rec.name}, MTTKRP on all {N} modes, FP64 COO loop, "
-                      f"{dt:.1f} s"}
+
+    def leg(fn, s0):
+        t0 = time.perf_counter()
+        for mode in range(N):
+            fn(rec.dims, coords[:, :s0], vals[:s0], init, mode)
+        dt = time.perf_counter() - t0
+        s = int(min(coords.shape[1], max(s0, s0 * seconds / max(dt, 1e-9))))
+        used = 1
+        t0 = time.perf_counter()
+        for mode in range(N):
+            r = fn(rec.dims, coords[:, :s], vals[:s], init, mode)
+            if isinstance(r, tuple):
+                used = r[1]
+        dt = time.perf_counter() - t0
+        return s, dt, used
+
+    s_all, dt_all, threads = leg(oracle.mttkrp_par, 1_000_000)
+    s_one, dt_one, _ = leg(oracle.mttkrp, 200_000)
+    return {"value": s_all * N / dt_all, "unit": "nnz/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {s_all} COO draws of {rec.name}, MTTKRP on all {N} modes, FP64 COO loop on "
+                      f"{threads} threads (OpenMP, private outputs), {dt_all:.1f} s",
+            "one_core": {"value": s_one * N / dt_one, "unit": "nnz/s", "cores": 1,
+                         "sample": f"first {s_one} COO draws, all {N} modes, one thread, {dt_one:.1f} s"},
+            "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
 if __name__ == "__main__":

@@ -99,6 +99,17 @@ typedef struct alto_info_t {
     double index_bytes;                    /* nnz * key_bits / 8 as stored */
     double coo_index_bytes;                /* nnz * N * 4 (uint32 COO coordinates) */
     double norm2;                          /* ||X||^2 in FP64 (sum of squared coalesced values) */
+    /* device memory the handle holds now, in bytes (it grows as MTTKRP
+     * plans are first used): */
+    double tensor_bytes;                   /* the ALTO tensor: index, values, byte tables */
+    double partition_bytes;                /* kept partitions: segment bounds, intervals,
+                                              coverage, segment lists */
+    double order_bytes;                    /* segment-local mode orders (`sorted`): per mode and
+                                              kept partition, a reordered copy of index and values */
+    double scratch_bytes;                  /* reusable workspace and per-XCD output replicas */
+    int flag_bit[ALTO_MAX_MODES];          /* index bit of the mode's helper flag (Section 3.3),
+                                              one of the spare bits at or above index_bits;
+                                              -1: the mode has none */
 } alto_info_t;
 
 /*
@@ -128,6 +139,23 @@ int alto_build(const uint32_t *const *coords, const float *vals, int64_t nnz,
  * dims, mode_bits, mask_lo and mask_hi of *out (other fields zero).
  * key_bits as in alto_opts.  Host only; needs no GPU. */
 int alto_layout(const uint64_t *dims, int N, int key_bits, alto_info_t *out);
+
+/*
+ * alto_append — add a batch of COO nonzeros to a built tensor (incremental
+ * format generation, for streaming decomposition, where a tensor grows batch
+ * by batch and the factors are refitted after each): the batch alone is
+ * linearized and radix-sorted (Section 3.1), merged with the tensor's
+ * ordered index in one pass, repeated coordinates are summed (the tensor's
+ * value first, then the batch's in input order, FP32), and the partition is
+ * rebuilt with the same requested segment count.  The result is bit for bit
+ * the tensor alto_build makes from the earlier COO input followed by the
+ * batch.  Arguments as for alto_build; the dims are the tensor's (every
+ * coordinate must be below them: ALTO_E_RANGE otherwise, with the tensor
+ * unchanged).  Segment-local orders and timed plans of the old tensor are
+ * dropped.  Synchronizes the stream.
+ */
+int alto_append(alto_tensor *t, const uint32_t *const *coords, const float *vals, int64_t nnz,
+                hipStream_t stream);
 
 /* alto_info — fill *out (host) with the tensor's description.  No device work. */
 int alto_info(const alto_tensor *t, alto_info_t *out);
@@ -261,6 +289,42 @@ int alto_export_mode_order(alto_tensor *t, int mode, void *keys_out, float *vals
 int alto_export_partition(const alto_tensor *t, int64_t *seg_out, uint32_t *ivl_out,
                           hipStream_t stream);
 int alto_export_coverage(const alto_tensor *t, int mode, uint32_t *cov_out, hipStream_t stream);
+
+/*
+ * alto_transpose — sparse tensor transposition, one of the operations the
+ * paper's related work (sparse tensor operations) names for the format:
+ * the tensor's nonzeros in lexicographic order of their coordinates taken
+ * in the mode order perm[0], perm[1], .., perm[N-1] (perm[0] most
+ * significant), as COO.  Each linearized index is rewritten as the
+ * lexicographic index of the permuted coordinates (the same B bits, grouped
+ * by mode), then one stable LSD radix sort over those B bits orders them.
+ *   perm        host, N distinct mode numbers.
+ *   coords_out  host array of N device pointers; coords_out[j] receives nnz
+ *               uint32 coordinates along mode perm[j].
+ *   vals_out    device, nnz floats.
+ * Allocates its own scratch (about 2 * (key_bits/8 + 4) bytes per nonzero)
+ * and synchronizes the stream before returning.
+ */
+int alto_transpose(const alto_tensor *t, const int *perm, uint32_t *const *coords_out, float *vals_out,
+                   hipStream_t stream);
+
+/*
+ * alto_export_flags — the helper flags of `mode` (Section 3.3: spare index
+ * bits marking a nonzero as internal, i.e. its mode-`mode` row is updated by
+ * no other unit of work, so the atomic strategy writes it without atomics).
+ * Here the unit is a lane group: the current partition's segment l of S
+ * nonzeros is cut into G groups, group g taking positions
+ * [floor(l*nnz/L) + floor(S*g/G), floor(l*nnz/L) + floor(S*(g+1)/G)), and a
+ * nonzero is flagged iff its row lies in the mode interval (min..max row,
+ * Section 3.2) of no other group.  Flags are computed by the first
+ * atomic-strategy MTTKRP of the mode on the partition (for the lane groups
+ * of that launch).
+ *   flags_out    device, nnz bytes (0/1) in the tensor's order; may be NULL.
+ *   lane_groups  host, receives G; may be NULL.
+ * ALTO_E_STATE if the mode has no flags for the current partition.
+ */
+int alto_export_flags(const alto_tensor *t, int mode, uint8_t *flags_out, int *lane_groups,
+                      hipStream_t stream);
 
 /*
  * alto_round_bf16 — storage rule for bfloat16 factors: each double is

@@ -28,7 +28,7 @@ EXPORTS = (
     "alto_build", "alto_info", "alto_partition", "alto_mttkrp", "cp_als", "alto_select",
     "alto_selector_load", "alto_selector_features", "alto_mlp_forward", "alto_mlp_backward",
     "alto_mlp_adam", "alto_export_keys", "alto_export_mode_order", "alto_export_partition", "alto_export_coverage",
-    "alto_round_bf16", "alto_free", "alto_last_error", "alto_device_compute_units", "alto_layout",
+    "alto_round_bf16", "alto_transpose", "alto_append", "alto_export_flags", "alto_free", "alto_last_error", "alto_device_compute_units", "alto_layout",
 )
 
 
@@ -54,6 +54,9 @@ class _Info(ctypes.Structure):
         ("mask_lo", ctypes.c_uint64 * MAX_MODES), ("mask_hi", ctypes.c_uint64 * MAX_MODES),
         ("fiber_reuse", ctypes.c_double * MAX_MODES), ("index_bytes", ctypes.c_double),
         ("coo_index_bytes", ctypes.c_double), ("norm2", ctypes.c_double),
+        ("tensor_bytes", ctypes.c_double), ("partition_bytes", ctypes.c_double),
+        ("order_bytes", ctypes.c_double), ("scratch_bytes", ctypes.c_double),
+        ("flag_bit", ctypes.c_int * MAX_MODES),
     ]
 
 
@@ -91,6 +94,9 @@ def lib():
     L.alto_export_partition.argtypes = [vp, vp, vp, vp]
     L.alto_export_coverage.argtypes = [vp, i32, vp, vp]
     L.alto_round_bf16.argtypes = [vp, vp, i64, vp]
+    L.alto_transpose.argtypes = [vp, vp, vp, vp, vp]
+    L.alto_append.argtypes = [vp, vp, vp, i64, vp]
+    L.alto_export_flags.argtypes = [vp, i32, vp, ctypes.POINTER(ctypes.c_int), vp]
     L.alto_free.argtypes = [vp]
     L.alto_free.restype = None
     L.alto_last_error.restype = ctypes.c_char_p
@@ -175,6 +181,19 @@ class AltoTensor:
         _check(lib().alto_build(rows, _ptr(vals), M, d, N, ctypes.byref(opts), ctypes.byref(h), _stream(stream)))
         return cls(h)
 
+    def append(self, coords, vals, stream=None):
+        """alto_append: add a batch (CUDA int32 coords [N, M], float32 vals [M])."""
+        torch = _torch()
+        N = self.info()["N"]
+        if coords.dim() != 2 or coords.shape[0] != N or coords.dtype != torch.int32 or not coords.is_cuda:
+            raise ValueError("coords must be a CUDA int32 tensor of shape [N, M]")
+        if vals.dtype != torch.float32 or not vals.is_cuda or vals.shape != (coords.shape[1],):
+            raise ValueError("vals must be a CUDA float32 tensor of shape [M]")
+        coords = coords.contiguous()
+        vals = vals.contiguous()
+        rows = _ptr_array([coords[n] for n in range(N)])
+        _check(self._lib.alto_append(self._h, rows, _ptr(vals), int(coords.shape[1]), _stream(stream)))
+
     def close(self):
         if self._h:
             self._lib.alto_free(self._h)
@@ -205,6 +224,9 @@ class AltoTensor:
             "masks": [int(inf.mask_lo[n]) | (int(inf.mask_hi[n]) << 64) for n in range(N)],
             "fiber_reuse": [float(inf.fiber_reuse[n]) for n in range(N)],
             "index_bytes": inf.index_bytes, "coo_index_bytes": inf.coo_index_bytes, "norm2": inf.norm2,
+            "tensor_bytes": inf.tensor_bytes, "partition_bytes": inf.partition_bytes,
+            "order_bytes": inf.order_bytes, "scratch_bytes": inf.scratch_bytes,
+            "flag_bit": [int(inf.flag_bit[n]) for n in range(N)],
         }
 
     @property
@@ -249,6 +271,32 @@ class AltoTensor:
         _check(self._lib.cp_als(self._h, R, iters, prec, _ptr_array(factors), _ptr(lam), fit, ctypes.byref(ex),
                                 _stream(stream)))
         return lam, np.array(fit[:iters], dtype=np.float64)
+
+    def transpose(self, perm, stream=None):
+        """alto_transpose: (coords int32 CUDA tensor [N, nnz] whose row j holds
+        the coordinates along mode perm[j], vals float32 [nnz]) in
+        lexicographic order of (perm[0], perm[1], ...)."""
+        torch = _torch()
+        inf = self.info()
+        N, M = inf["N"], inf["nnz"]
+        if sorted(perm) != list(range(N)):
+            raise ValueError("perm must be a permutation of 0..N-1")
+        dev = torch.device("cuda", torch.cuda.current_device())
+        coords = torch.empty((N, M), dtype=torch.int32, device=dev)
+        vals = torch.empty(M, dtype=torch.float32, device=dev)
+        p = (ctypes.c_int * N)(*perm)
+        _check(self._lib.alto_transpose(self._h, p, _ptr_array([coords[j] for j in range(N)]), _ptr(vals),
+                                        _stream(stream)))
+        return coords, vals
+
+    def export_flags(self, mode: int, stream=None):
+        """alto_export_flags: (flags uint8 CUDA tensor [nnz], lane groups per segment)."""
+        torch = _torch()
+        M = self.info()["nnz"]
+        out = torch.empty(M, dtype=torch.uint8, device=torch.device("cuda", torch.cuda.current_device()))
+        g = ctypes.c_int(0)
+        _check(self._lib.alto_export_flags(self._h, mode, _ptr(out), ctypes.byref(g), _stream(stream)))
+        return out, g.value
 
     def select(self, mode: int, R: int, prec: str = "f32"):
         ex = _Exec()

@@ -68,6 +68,20 @@ int make_layout(alto_tensor *t, int key_bits_req) {
     if (pos > t->key_bits)
         return set_error(ALTO_E_TOO_WIDE, "linearized index needs " + std::to_string(pos) + " bits, key has " +
                                               std::to_string(t->key_bits));
+    // helper-flag bits: the spare index bits go to the longest modes first
+    // (fewest nonzeros per row); a flagged row also needs a free bit 31
+    {
+        int by_len[kMaxModes];
+        for (int n = 0; n < N; n++) {
+            by_len[n] = n;
+            t->flag_bit[n] = -1;
+            t->flag_L[n] = t->flag_NG[n] = 0;
+        }
+        std::stable_sort(by_len, by_len + N, [&](int a, int b) { return t->dims[a] > t->dims[b]; });
+        int next = pos;
+        for (int q = 0; q < N && next < t->key_bits; q++)
+            if (t->dims[by_len[q]] < 0x80000000ull) t->flag_bit[by_len[q]] = next++;
+    }
     // runs of consecutive positions, split at the 64-bit word boundary
     t->tab.N = N;
     for (int n = 0; n < N; n++) {
@@ -237,13 +251,17 @@ constexpr size_t kSparePartitions = 3;
 int select_partition(alto_tensor *t, int L, hipStream_t s) {
     if (L <= 0) L = 8 * cu_count();
     const int Le = t->nnz == 0 ? 0 : (int)std::min<int64_t>(L, t->nnz);
-    if (t->part && t->part->L == Le) return ALTO_OK;
+    if (t->part && t->part->L == Le) {
+        t->part->L_req = L;
+        return ALTO_OK;
+    }
     for (size_t q = 0; q < t->spare.size(); q++)
         if (t->spare[q]->L == Le) {
             std::unique_ptr<Partition> p = std::move(t->spare[q]);
             t->spare.erase(t->spare.begin() + q);
             if (t->part) t->spare.push_back(std::move(t->part));
             t->part = std::move(p);
+            t->part->L_req = L;
             return ALTO_OK;
         }
     std::unique_ptr<Partition> p;
@@ -257,6 +275,7 @@ int select_partition(alto_tensor *t, int L, hipStream_t s) {
         t->spare.push_back(std::move(t->part));
     }
     t->part = std::move(p);
+    t->part->L_req = L;
     return ALTO_OK;
 }
 
@@ -337,6 +356,8 @@ int check_tensor(const alto_tensor *t) {
 
 }  // namespace
 
+int make_partition(alto_tensor *t, int L, hipStream_t s) { return select_partition(t, L, s); }
+
 int ensure_workspace(alto_tensor *t, size_t bytes) {
     if (t->ws_bytes >= bytes) return ALTO_OK;
     if (t->ws) ALTO_HIP(hipFree(t->ws));
@@ -413,55 +434,31 @@ int resolve_strategy(alto_tensor *t, const void *const *factors, int R, int prec
     return ALTO_OK;
 }
 
-int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int prec, int mode, float *out,
-                        const alto_exec *ex, hipStream_t s) {
+int check_mttkrp_args(const alto_tensor *t, const void *const *factors, int R, int prec, int mode,
+                      const float *out) {
     int rc = check_tensor(t);
     if (rc) return rc;
     if (mode < 0 || mode >= t->N) return set_error(ALTO_E_INVAL, "mode out of range");
     if (R < 1 || R > ALTO_MAX_RANK) return set_error(ALTO_E_INVAL, "R must be in 1..256");
     if (prec != ALTO_PREC_F32 && prec != ALTO_PREC_BF16) return set_error(ALTO_E_INVAL, "unknown precision");
     if (!out || !factors) return set_error(ALTO_E_INVAL, "null output or factor array");
+    // row 2^32-1 would alias the kernels' "no row" marker
+    if (t->dims[mode] > 0xffffffffull)
+        return set_error(ALTO_E_INVAL, "MTTKRP output mode must have fewer than 2^32 rows");
     for (int m = 0; m < t->N; m++)
         if (m != mode && !factors[m]) return set_error(ALTO_E_INVAL, "null factor pointer");
     // rank-specialized kernels gather rows with 16-byte loads
     for (int m = 0; m < t->N; m++)
         if (m != mode && ((uintptr_t)factors[m] & 15u)) return set_error(ALTO_E_INVAL, "factor pointer not 16-byte aligned");
     if ((uintptr_t)out & 15u) return set_error(ALTO_E_INVAL, "output pointer not 16-byte aligned");
-    alto_exec plan;
-    rc = resolve_strategy(t, factors, R, prec, mode, out, ex, s, &plan);
-    if (rc) return rc;
-    if (plan.num_segments > 0) {
-        rc = select_partition(t, plan.num_segments, s);
-        if (rc) return rc;
-    }
-    const uint64_t outn = t->dims[mode] * (uint64_t)R;
-    ALTO_HIP(hipMemsetAsync(out, 0, sizeof(float) * outn, s));
-    if (t->nnz == 0) return ALTO_OK;
-    const bool sorted = plan.strategy == ALTO_STRATEGY_SORTED;
-    if (sorted) {
-        rc = build_mode_order(t, mode, s);
-        if (rc) return rc;
-    }
-    SegLists *sl = nullptr;
-    rc = build_lists(t, mode, sorted ? ALTO_STRATEGY_ATOMIC : plan.strategy, R, prec, &sl);
-    if (rc) return rc;
-    // per-XCD replicas for the atomic updates when they are cheap next to the
-    // nonzero traffic (ALTO_REPLICAS=0/1 forces the choice)
-    const int nxcc = device_xcc_count();
-    const size_t rep_bytes = (size_t)nxcc * outn * sizeof(float);
-    const long force = env_long("ALTO_REPLICAS", -1);
-    bool use_rep = !sorted && nxcc > 1 && rep_bytes <= ((size_t)2 << 30) && rep_bytes <= (size_t)t->nnz * 16;
-    if (force == 0) use_rep = false;
-    if (force == 1) use_rep = nxcc > 1;
-    if (use_rep && t->rep_bytes < rep_bytes) {
-        if (t->rep) ALTO_HIP(hipFree(t->rep));
-        t->rep = nullptr;
-        t->rep_bytes = 0;
-        ALTO_HIP(hipMalloc(&t->rep, rep_bytes));
-        t->rep_bytes = rep_bytes;
-    }
-    if (use_rep) ALTO_HIP(hipMemsetAsync(t->rep, 0, rep_bytes, s));
-    MtLaunch a{};
+    return ALTO_OK;
+}
+
+int fill_mt_launch(const alto_tensor *t, const void *const *factors, int R, int prec, int mode, bool sorted,
+                   MtLaunch *out) {
+    MtLaunch &a = *out;
+    a = MtLaunch{};
+    a.dec.fbit = -1;
     a.keys = sorted ? t->part->okeys[mode] : t->keys;
     a.vals = sorted ? t->part->ovals[mode] : t->vals;
     a.seg = t->part->d_seg;
@@ -516,23 +513,121 @@ int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int p
             used += bytes;
         }
     }
+    a.threads = a.dec.smask ? 1024 : atomic_threads(t->part->L);
+    return ALTO_OK;
+}
+
+// Helper flags of `mode` for the current partition cut into NG lane groups
+// per segment (the unit that walks its nonzeros in order): flag set iff the
+// nonzero's row lies in the mode interval of no other lane group's range
+// (Section 3.2's coverage, computed over those ranges).  Computed once per
+// (partition, NG) and kept in the index's spare bit.
+int ensure_flags(alto_tensor *t, int mode, int NG, hipStream_t s) {
+    Partition &P = *t->part;
+    if (t->flag_bit[mode] < 0 || t->nnz == 0 || P.L == 0) return ALTO_OK;
+    if (t->flag_L[mode] == P.L && t->flag_NG[mode] == NG) return ALTO_OK;
+    const int64_t Lm = (int64_t)P.L * NG;
+    if (Lm > 0x7fffffff) return ALTO_OK;
+    std::vector<int64_t> h(Lm + 1);
+    for (int l = 0; l < P.L; l++) {
+        const int64_t sb = P.h_seg[l], S = P.h_seg[l + 1] - sb;
+        for (int g = 0; g < NG; g++) h[(int64_t)l * NG + g] = sb + (S * g) / NG;
+    }
+    h[Lm] = t->nnz;
+    int64_t *d_seg = nullptr;
+    uint32_t *d_ivl = nullptr, *d_cov = nullptr;
+    auto done = [&](int rc) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(d_seg);
+        (void)hipFree(d_ivl);
+        (void)hipFree(d_cov);
+        return rc;
+    };
+    hipError_t e = hipMalloc(&d_seg, sizeof(int64_t) * (Lm + 1));
+    if (e == hipSuccess) e = hipMalloc(&d_ivl, sizeof(uint32_t) * Lm * t->N * 2);
+    if (e == hipSuccess) e = hipMalloc(&d_cov, sizeof(uint32_t) * t->dims[mode]);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_seg, h.data(), sizeof(int64_t) * (Lm + 1), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return done(hip_error(e, "helper flags"));
+    int rc = launch_intervals(t->key_bits, t->keys, d_seg, (int)Lm, t->tab, t->ctab, d_ivl, s);
+    if (rc) return done(rc);
+    rc = ensure_workspace(t, coverage_scratch(t->dims[mode]));
+    if (rc) return done(rc);
+    rc = coverage(t->N, (int)Lm, d_ivl, mode, t->dims[mode], d_cov, t->ws, t->ws_bytes, s);
+    if (rc) return done(rc);
+    rc = launch_set_flags(t->key_bits, t->keys, t->nnz, t->tab, t->ctab, mode, d_cov, t->flag_bit[mode], s);
+    if (rc) return done(rc);
+    t->flags_in_keys = true;
+    t->flag_L[mode] = P.L;
+    t->flag_NG[mode] = NG;
+    return done(ALTO_OK);
+}
+
+int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int prec, int mode, float *out,
+                        const alto_exec *ex, hipStream_t s) {
+    int rc = check_mttkrp_args(t, factors, R, prec, mode, out);
+    if (rc) return rc;
+    alto_exec plan;
+    rc = resolve_strategy(t, factors, R, prec, mode, out, ex, s, &plan);
+    if (rc) return rc;
+    if (plan.num_segments > 0) {
+        rc = select_partition(t, plan.num_segments, s);
+        if (rc) return rc;
+    }
+    const uint64_t outn = t->dims[mode] * (uint64_t)R;
+    ALTO_HIP(hipMemsetAsync(out, 0, sizeof(float) * outn, s));
+    if (t->nnz == 0) return ALTO_OK;
+    const bool sorted = plan.strategy == ALTO_STRATEGY_SORTED;
+    if (sorted) {
+        rc = build_mode_order(t, mode, s);
+        if (rc) return rc;
+    }
+    SegLists *sl = nullptr;
+    rc = build_lists(t, mode, sorted ? ALTO_STRATEGY_ATOMIC : plan.strategy, R, prec, &sl);
+    if (rc) return rc;
+    // the strategies that visit the nonzeros in linearized order accumulate
+    // their atomic updates in FP64 (see mttkrp_k); the segment-local order
+    // makes one FP32 atomic per (segment, row) run, directly into out
+    const bool fp64 = !sorted;
+    const size_t acc_bytes = fp64 ? sizeof(double) * outn : 0;
+    if (fp64 && t->acc64_bytes < acc_bytes) {
+        if (t->acc64) ALTO_HIP(hipFree(t->acc64));
+        t->acc64 = nullptr;
+        t->acc64_bytes = 0;
+        ALTO_HIP(hipMalloc(&t->acc64, acc_bytes));
+        t->acc64_bytes = acc_bytes;
+    }
+    if (fp64) ALTO_HIP(hipMemsetAsync(t->acc64, 0, acc_bytes, s));
+    MtLaunch a;
+    rc = fill_mt_launch(t, factors, R, prec, mode, sorted, &a);
+    if (rc) return rc;
     a.out = out;
-    a.rep = use_rep ? t->rep : nullptr;
-    a.rep_stride = outn;
-    a.nrep = use_rep ? nxcc : 0;
+    a.acc64 = fp64 ? t->acc64 : nullptr;
+    const int atomic_wg = a.threads;
+    // helper flags for the launches that update the output with atomics on
+    // the linearized order (ALTO_HELPER_FLAGS=0 turns them off)
+    a.dec.fbit = -1;
+    if (!sorted && sl->n_atomic > 0 && t->flag_bit[mode] >= 0 && env_long("ALTO_HELPER_FLAGS", 1) != 0) {
+        const int G = mt_group_lanes(R, prec);
+        rc = ensure_flags(t, mode, atomic_wg / G, s);
+        if (rc) return rc;
+        if (t->flag_L[mode] == t->part->L && t->flag_NG[mode] == atomic_wg / G) a.dec.fbit = t->flag_bit[mode];
+    }
     auto run = [&](const int32_t *list, int n, int staged, int rows) -> int {
         a.list = list;
         a.n_list = n;
         a.staged = staged;
         a.temp_rows = rows;
-        a.threads = staged ? staged_threads((size_t)rows * temp_stride(R) * 4)
-                           : (a.dec.smask ? 1024 : atomic_threads(t->part->L));
-        return launch_mt(a, t->key_bits, prec, s);
+        a.threads = staged ? staged_threads((size_t)rows * temp_stride(R) * 4) : atomic_wg;
+        const int fbit = a.dec.fbit;
+        if (staged) a.dec.fbit = -1;
+        const int rc2 = launch_mt(a, t->key_bits, prec, s);
+        a.dec.fbit = fbit;
+        return rc2;
     };
     if (getenv("ALTO_DEBUG_PLAN"))
-        fprintf(stderr, "[alto] mode %d R %d prec %d strategy %d L %d: atomic %d, staged %d/%d/%d (rows <= %d/%d/%d), replicas %d\n",
+        fprintf(stderr, "[alto] mode %d R %d prec %d strategy %d L %d: atomic %d, staged %d/%d/%d (rows <= %d/%d/%d), fp64 %d, flags %d\n",
                 mode, R, prec, plan.strategy, t->part->L, sl->n_atomic, sl->n_bucket[0], sl->n_bucket[1],
-                sl->n_bucket[2], sl->w_bucket[0], sl->w_bucket[1], sl->w_bucket[2], use_rep ? nxcc : 0);
+                sl->n_bucket[2], sl->w_bucket[0], sl->w_bucket[1], sl->w_bucket[2], (int)fp64, a.dec.fbit >= 0);
     const int32_t *p = sl->d;
     const int32_t *bucket_p = p + sl->n_atomic;
     for (int b = 0; b < SegLists::kBuckets; b++) {
@@ -542,7 +637,7 @@ int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int p
     }
     rc = run(p, sl->n_atomic, 0, 0);
     if (rc) return rc;
-    if (use_rep) return launch_replica_reduce(out, t->rep, outn, nxcc, outn, s);
+    if (fp64) return launch_acc64_finish(out, t->acc64, outn, s);
     return ALTO_OK;
 }
 
@@ -712,6 +807,29 @@ int alto_info(const alto_tensor *t, alto_info_t *out) {
     out->index_bytes = (double)t->nnz * t->key_bits / 8.0;
     out->coo_index_bytes = (double)t->nnz * t->N * 4.0;
     out->norm2 = t->norm2;
+    const double kb = t->key_bits / 8.0;
+    out->tensor_bytes = (double)t->nnz * (kb + 4.0) + (double)t->h_ctab.size() + (double)t->h_etab.size();
+    auto part_bytes = [&](const Partition &p, double *orders) {
+        double b = 8.0 * (p.L + 1) + 8.0 * p.L * t->N;
+        for (int n = 0; n < t->N; n++) {
+            if (p.d_cov[n]) b += 4.0 * (double)t->dims[n];
+            if (p.okeys[n]) *orders += (double)t->nnz * (kb + 4.0);
+        }
+        for (const auto &kv : p.lists) {
+            const SegLists &sl = kv.second;
+            int n = sl.n_atomic;
+            for (int q = 0; q < SegLists::kBuckets; q++) n += sl.n_bucket[q];
+            b += 4.0 * std::max(1, n);
+        }
+        return b;
+    };
+    double orders = 0.0, parts = 0.0;
+    if (t->part) parts += part_bytes(*t->part, &orders);
+    for (const auto &p : t->spare) parts += part_bytes(*p, &orders);
+    out->partition_bytes = parts;
+    out->order_bytes = orders;
+    out->scratch_bytes = (double)t->ws_bytes + (double)t->acc64_bytes;
+    for (int n = 0; n < t->N; n++) out->flag_bit[n] = t->flag_bit[n];
     return ALTO_OK;
 }
 
@@ -732,9 +850,27 @@ int alto_export_keys(const alto_tensor *t, void *keys_out, float *vals_out, hipS
     g_err.clear();
     if (!t) return set_error(ALTO_E_INVAL, "null tensor handle");
     if (t->nnz == 0) return ALTO_OK;
-    if (keys_out)
-        ALTO_HIP(hipMemcpyAsync(keys_out, t->keys, (size_t)t->nnz * t->key_bits / 8, hipMemcpyDeviceToDevice, s));
+    if (keys_out) {
+        // helper-flag bits are not part of the index
+        if (t->flags_in_keys) {
+            const int rc = launch_mask_keys(t->key_bits, t->keys, t->nnz, t->B, keys_out, s);
+            if (rc) return rc;
+        } else {
+            ALTO_HIP(hipMemcpyAsync(keys_out, t->keys, (size_t)t->nnz * t->key_bits / 8, hipMemcpyDeviceToDevice, s));
+        }
+    }
     if (vals_out) ALTO_HIP(hipMemcpyAsync(vals_out, t->vals, sizeof(float) * t->nnz, hipMemcpyDeviceToDevice, s));
+    return ALTO_OK;
+}
+
+int alto_export_flags(const alto_tensor *t, int mode, uint8_t *flags_out, int *lane_groups, hipStream_t s) {
+    g_err.clear();
+    if (!t) return set_error(ALTO_E_INVAL, "null tensor handle");
+    if (mode < 0 || mode >= t->N) return set_error(ALTO_E_INVAL, "mode out of range");
+    if (t->flag_bit[mode] < 0 || t->flag_L[mode] == 0 || !t->part || t->flag_L[mode] != t->part->L)
+        return set_error(ALTO_E_STATE, "no helper flags of this mode for the current partition");
+    if (lane_groups) *lane_groups = t->flag_NG[mode];
+    if (t->nnz > 0 && flags_out) return launch_get_flags(t->key_bits, t->keys, t->nnz, t->flag_bit[mode], flags_out, s);
     return ALTO_OK;
 }
 
@@ -747,8 +883,15 @@ int alto_export_mode_order(alto_tensor *t, int mode, void *keys_out, float *vals
     rc = build_mode_order(t, mode, s);
     if (rc) return rc;
     const Partition &P = *t->part;
-    if (keys_out)
-        ALTO_HIP(hipMemcpyAsync(keys_out, P.okeys[mode], (size_t)t->nnz * t->key_bits / 8, hipMemcpyDeviceToDevice, s));
+    if (keys_out) {
+        if (t->flags_in_keys) {
+            rc = launch_mask_keys(t->key_bits, P.okeys[mode], t->nnz, t->B, keys_out, s);
+            if (rc) return rc;
+        } else {
+            ALTO_HIP(hipMemcpyAsync(keys_out, P.okeys[mode], (size_t)t->nnz * t->key_bits / 8,
+                                    hipMemcpyDeviceToDevice, s));
+        }
+    }
     if (vals_out) ALTO_HIP(hipMemcpyAsync(vals_out, P.ovals[mode], sizeof(float) * t->nnz, hipMemcpyDeviceToDevice, s));
     return ALTO_OK;
 }
@@ -789,7 +932,7 @@ void alto_free(alto_tensor *t) {
     (void)hipDeviceSynchronize();
     t->part.reset();
     t->spare.clear();
-    (void)hipFree(t->rep);
+    (void)hipFree(t->acc64);
     (void)hipFree(t->keys);
     (void)hipFree(t->ctab);
     (void)hipFree(t->etab);

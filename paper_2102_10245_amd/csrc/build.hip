@@ -650,6 +650,7 @@ __global__ __launch_bounds__(kThreads) void coverage_marks_k(const uint32_t *__r
     if (l >= L) return;
     const uint32_t s = ivl[((int64_t)l * N + mode) * 2 + 0];
     const uint32_t e = ivl[((int64_t)l * N + mode) * 2 + 1];
+    if (s > e) return;  // an empty range of nonzeros has no interval (it reads as [2^32-1, 0])
     atomicAdd(&diff[s], 1);
     atomicAdd(&diff[(uint64_t)e + 1], -1);
 }
@@ -687,7 +688,112 @@ unsigned grid_for(int64_t n, int per_block) {
 
 }  // namespace
 
+// ------------------------------------------------------------ helper flags
+template <typename K>
+__device__ __forceinline__ K with_bit(K k, int pos, bool v) {
+    const K b = (K)1 << pos;
+    return v ? (k | b) : (k & ~b);
+}
+template <>
+__device__ __forceinline__ u128 with_bit<u128>(u128 k, int pos, bool v) {
+    uint64_t &w = pos < 64 ? k.lo : k.hi;
+    const uint64_t b = 1ull << (pos & 63);
+    w = v ? (w | b) : (w & ~b);
+    return k;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kThreads) void set_flags_k(K *__restrict__ keys, int64_t n, RunTable tab,
+                                                         const K *__restrict__ ctab, int mode,
+                                                         const uint32_t *__restrict__ cov, int fbit) {
+    constexpr int kTab = byte_table_entries(8 * (int)sizeof(K));
+    __shared__ K lt[kTab > 0 ? kTab : 1];
+    if constexpr (kTab > 0) {
+        for (int q = threadIdx.x; q < kTab; q += kThreads) lt[q] = ctab[q];
+        __syncthreads();
+    }
+    for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < n; x += (int64_t)gridDim.x * kThreads) {
+        const K key = keys[x];
+        uint32_t row;
+        if constexpr (kTab > 0) row = (uint32_t)(compact_index(key, lt) >> tab.coff[mode]) & tab.cmask[mode];
+        else row = extract_mode(key, tab, mode);
+        keys[x] = with_bit(key, fbit, cov[row] == 1u);
+    }
+}
+
+template <typename K>
+__global__ __launch_bounds__(kThreads) void mask_keys_k(const K *__restrict__ keys, int64_t n, K keep,
+                                                         K *__restrict__ out) {
+    for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < n; x += (int64_t)gridDim.x * kThreads)
+        out[x] = keys[x] & keep;
+}
+template <>
+__global__ __launch_bounds__(kThreads) void mask_keys_k<u128>(const u128 *__restrict__ keys, int64_t n, u128 keep,
+                                                               u128 *__restrict__ out) {
+    for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < n; x += (int64_t)gridDim.x * kThreads) {
+        const u128 k = keys[x];
+        out[x] = u128{k.lo & keep.lo, k.hi & keep.hi};
+    }
+}
+
+template <typename K>
+__global__ __launch_bounds__(kThreads) void get_flags_k(const K *__restrict__ keys, int64_t n, int fbit,
+                                                         uint8_t *__restrict__ out) {
+    for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < n; x += (int64_t)gridDim.x * kThreads) {
+        const K k = keys[x];
+        uint32_t b;
+        if constexpr (sizeof(K) == 16) {
+            const u128 &w = reinterpret_cast<const u128 &>(k);
+            b = (uint32_t)((fbit < 64 ? w.lo : w.hi) >> (fbit & 63)) & 1u;
+        } else {
+            b = (uint32_t)(k >> fbit) & 1u;
+        }
+        out[x] = (uint8_t)b;
+    }
+}
+
 // ------------------------------------------------------------ launchers
+int launch_get_flags(int key_bits, const void *keys, int64_t n, int fbit, uint8_t *out, hipStream_t s) {
+    if (n <= 0) return ALTO_OK;
+    const unsigned g = std::min<unsigned>(grid_for(n, kThreads * 4), 4096);
+    if (key_bits == 32) get_flags_k<uint32_t><<<g, kThreads, 0, s>>>((const uint32_t *)keys, n, fbit, out);
+    else if (key_bits == 64) get_flags_k<uint64_t><<<g, kThreads, 0, s>>>((const uint64_t *)keys, n, fbit, out);
+    else get_flags_k<u128><<<g, kThreads, 0, s>>>((const u128 *)keys, n, fbit, out);
+    ALTO_HIP(hipGetLastError());
+    return ALTO_OK;
+}
+
+int launch_set_flags(int key_bits, void *keys, int64_t n, const RunTable &tab, const void *ctab, int mode,
+                     const uint32_t *cov, int fbit, hipStream_t s) {
+    if (n <= 0) return ALTO_OK;
+    if (key_bits <= 64 && !ctab) return set_error(ALTO_E_INVAL, "internal: missing byte tables");
+    const unsigned g = std::min<unsigned>(grid_for(n, kThreads * 4), 4096);
+    if (key_bits == 32)
+        set_flags_k<uint32_t><<<g, kThreads, 0, s>>>((uint32_t *)keys, n, tab, (const uint32_t *)ctab, mode, cov, fbit);
+    else if (key_bits == 64)
+        set_flags_k<uint64_t><<<g, kThreads, 0, s>>>((uint64_t *)keys, n, tab, (const uint64_t *)ctab, mode, cov, fbit);
+    else set_flags_k<u128><<<g, kThreads, 0, s>>>((u128 *)keys, n, tab, nullptr, mode, cov, fbit);
+    ALTO_HIP(hipGetLastError());
+    return ALTO_OK;
+}
+
+int launch_mask_keys(int key_bits, const void *keys, int64_t n, int B, void *out, hipStream_t s) {
+    if (n <= 0) return ALTO_OK;
+    const unsigned g = std::min<unsigned>(grid_for(n, kThreads * 4), 4096);
+    if (key_bits == 32) {
+        const uint32_t keep = B >= 32 ? 0xffffffffu : ((1u << B) - 1u);
+        mask_keys_k<uint32_t><<<g, kThreads, 0, s>>>((const uint32_t *)keys, n, keep, (uint32_t *)out);
+    } else if (key_bits == 64) {
+        const uint64_t keep = B >= 64 ? ~0ull : ((1ull << B) - 1ull);
+        mask_keys_k<uint64_t><<<g, kThreads, 0, s>>>((const uint64_t *)keys, n, keep, (uint64_t *)out);
+    } else {
+        const u128 keep{B >= 64 ? ~0ull : ((1ull << B) - 1ull), B >= 128 ? ~0ull : (B <= 64 ? 0ull : ((1ull << (B - 64)) - 1ull))};
+        mask_keys_k<u128><<<g, kThreads, 0, s>>>((const u128 *)keys, n, keep, (u128 *)out);
+    }
+    ALTO_HIP(hipGetLastError());
+    return ALTO_OK;
+}
+
 int launch_encode(int key_bits, const CoordPtrs &c, const uint64_t *dims, int64_t n, const RunTable &tab,
                   const void *etab, void *keys, int *d_flag, hipStream_t s) {
     if (n <= 0) return ALTO_OK;

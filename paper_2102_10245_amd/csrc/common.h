@@ -149,6 +149,7 @@ struct SegLists {
 // and segment-local mode orders.  Owns its device memory.
 struct Partition {
     int L = 0;
+    int L_req = 0;  // the segment count asked for (L is capped at nnz)
     int64_t *d_seg = nullptr;         // L+1
     uint32_t *d_ivl = nullptr;        // L*N*2
     uint32_t *d_cov[kMaxModes] = {};  // per mode, I_n
@@ -201,12 +202,22 @@ struct alto_tensor {
     // reusable device workspace (grown on demand)
     void *ws = nullptr;
     size_t ws_bytes = 0;
-    // per-XCD output replicas for atomic updates (grown on demand)
-    float *rep = nullptr;
-    size_t rep_bytes = 0;
+    // FP64 accumulator of the atomic updates of the linearized-order
+    // strategies, I_mode x R doubles (grown on demand)
+    double *acc64 = nullptr;
+    size_t acc64_bytes = 0;
     // plans found by timing every candidate, for (mode, R, prec) outside the
     // selector's training range (see tuned_key)
     std::map<uint64_t, alto_exec> tuned;
+    // Helper flags (Section 3.3): index bit flag_bit[n] (one of the spare
+    // bits at or above B; -1: none) marks the nonzeros whose mode-n row no
+    // other lane group touches, so their atomic-strategy updates are plain
+    // writes.  Valid for the current index order cut into flag_L segments of
+    // flag_NG lane groups each (flag_L = 0: not computed).
+    int flag_bit[alto::kMaxModes] = {-1, -1, -1, -1, -1, -1, -1, -1};
+    int flag_L[alto::kMaxModes] = {};
+    int flag_NG[alto::kMaxModes] = {};
+    bool flags_in_keys = false;  // some flag bit may be set in keys
 };
 
 namespace alto {
@@ -236,6 +247,13 @@ int coverage(int N, int L, const uint32_t *d_ivl, int mode, uint64_t dim, uint32
              size_t scratch_bytes, hipStream_t s);
 size_t coverage_scratch(uint64_t dim);
 int launch_sumsq(const float *vals, int64_t n, double *out, hipStream_t s);
+// helper flags: bit `fbit` of every index := cov[row along mode] == 1
+int launch_set_flags(int key_bits, void *keys, int64_t n, const RunTable &tab, const void *ctab, int mode,
+                     const uint32_t *cov, int fbit, hipStream_t s);
+// out[x] = bit fbit of index x
+int launch_get_flags(int key_bits, const void *keys, int64_t n, int fbit, uint8_t *out, hipStream_t s);
+// out = keys with every bit at or above B cleared (out may equal keys)
+int launch_mask_keys(int key_bits, const void *keys, int64_t n, int B, void *out, hipStream_t s);
 // segment-local order by `mode` (scratch: seg_order_scratch bytes)
 size_t seg_order_scratch(int key_bits, int64_t n);
 int launch_seg_order(int key_bits, const void *keys, const float *vals, const int64_t *seg, int L,
@@ -275,6 +293,8 @@ inline uint64_t tuned_key(int mode, int R, int prec) {
 int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int prec, int mode, float *out,
                         const alto_exec *ex, hipStream_t s);
 int ensure_workspace(alto_tensor *t, size_t bytes);
+// make the partition into L segments current (0: 8 per compute unit)
+int make_partition(alto_tensor *t, int L, hipStream_t s);
 
 // ---------------------------------------------------------------- device helpers
 __device__ __forceinline__ uint64_t lanemask_lt() {

@@ -975,6 +975,9 @@ int cp_als_impl(alto_tensor *t, int R, int iters, int prec, void *const *factors
     for (int n = 0; n < t->N; n++)
         if (!factors[n]) return set_error(ALTO_E_INVAL, "null factor pointer");
     if (t->nnz == 0) return set_error(ALTO_E_INVAL, "CP-ALS of an empty tensor");
+    for (int n = 0; n < t->N; n++)
+        if (t->dims[n] > 0xffffffffull)
+            return set_error(ALTO_E_INVAL, "CP-ALS needs every mode to have fewer than 2^32 rows");
     const int N = t->N;
     uint64_t maxI = 0;
     for (int n = 0; n < N; n++) maxI = std::max(maxI, t->dims[n]);

@@ -19,16 +19,16 @@
 //     repeats; when the row changes the accumulator is flushed.
 // A flush goes either to Temp (Algorithm 2, local staging: LDS rows
 // [T^s, T^e] of the segment's mode interval, merged into the output when the
-// segment is done: plain stores for rows no other segment covers, FP32 atomics
-// otherwise) or out with FP32 atomics (Algorithm 2, atomic update).  Atomic
+// segment is done: plain stores for rows no other segment covers, atomics
+// otherwise) or out with atomics (Algorithm 2, atomic update).  Atomic
 // flushes are queued in LDS and drained by the whole wave with R consecutive
-// lanes per output row, so each atomic instruction covers whole 128-byte
-// lines (on this GPU global atomics cost per line touched); queue entries of
-// one row at consecutive slots are summed first.  They can target a per-XCD
-// replica of the output (chosen by the XCC id register) so that the lines a
-// replica owns are only ever touched by one L2; a reduction adds the
-// replicas into the output afterwards.  The atomics are device-scope either
-// way, so the result does not depend on which XCD a workgroup runs on.
+// lanes per output row, so each atomic instruction covers whole lines (on
+// this GPU global atomics cost per line touched); queue entries of one row
+// at consecutive slots are summed first.  When the nonzeros come in
+// linearized order the atomics are FP64, into an accumulator added into the
+// output afterwards (precision: see gadd).  Rows that the helper flags
+// (Section 3.3) mark as this lane group's alone skip the queue and are
+// written with plain read-modify-writes.
 #pragma once
 
 #include <type_traits>
@@ -49,6 +49,7 @@ struct FactorPtrs {
 // modes with bit j of smask have their whole factor matrix (sbytes[j] bytes)
 // copied to LDS at byte offset soff[j] and are gathered from there.
 struct ModeDec {
+    int fbit;  // index bit of the output mode's helper flag (-1: no flags)
     int om[kMaxModes];
     uint32_t coff[kMaxModes];
     uint32_t cmask[kMaxModes];
@@ -83,7 +84,17 @@ __device__ __forceinline__ uint32_t group_bcast(uint32_t x) {
 }
 
 constexpr uint32_t kNoRow = 0xffffffffu;
-constexpr int kMaxReplicas = 16;
+// with helper flags the output row carries its flag in bit 31 (rows < 2^31 - 1)
+constexpr uint32_t kOwnBit = 0x80000000u;
+
+template <typename K>
+__device__ __forceinline__ uint32_t key_bit(const K &k, int pos) {
+    return (uint32_t)(k >> pos) & 1u;
+}
+template <>
+__device__ __forceinline__ uint32_t key_bit<u128>(const u128 &k, int pos) {
+    return (uint32_t)((pos < 64 ? k.lo : k.hi) >> (pos & 63)) & 1u;
+}
 
 template <typename FT>
 struct FactorLoad;
@@ -159,17 +170,13 @@ __host__ __device__ constexpr int mt_queue_bytes(int threads) {
     return C::kQueue ? (threads / 64) * C::kQRows * (RT + 1) * 4 : 0;
 }
 
-__device__ __forceinline__ uint32_t xcc_id() {
-    // hwreg(HW_REG_XCC_ID, 0, 4): id 20, offset 0, 4 bits
-    return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 0xfu;
-}
 
 template <typename K, int NT, int RT, typename FT, bool kStaged, bool kWide>
 __global__ __launch_bounds__(1024) void mttkrp_k(
     const K *__restrict__ keys, const float *__restrict__ vals, const int64_t *__restrict__ seg,
     const uint32_t *__restrict__ ivl, const uint32_t *__restrict__ cov, FactorPtrs fac, int R_rt, int N_rt, int mode,
-    RunTable tab, ModeDec dec, const K *__restrict__ ctab, int ctab_off, float *__restrict__ out, float *__restrict__ rep,
-    uint64_t rep_stride, int nrep, const int32_t *__restrict__ seg_list, int n_list) {
+    RunTable tab, ModeDec dec, const K *__restrict__ ctab, int ctab_off, float *__restrict__ out,
+    double *__restrict__ acc64, const int32_t *__restrict__ seg_list, int n_list) {
     using C = MtCfg<NT, RT, FT>;
     constexpr int VEC = C::kVec, G = C::kG, GPW = C::kGPW, NM = C::kNMax, NCOL = C::kCols, U = C::kU;
     constexpr int NO = NM - 1;  // other modes
@@ -186,7 +193,7 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
     const int per = (n_list + 7) / 8;
     const int li = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (li >= n_list) return;
-    const int l = seg_list[li];
+    const int l = seg_list ? seg_list[li] : li;  // no list: segments 0 .. n_list-1
 
     const int64_t sb = seg[l], S = seg[l + 1] - sb;
     const int lane = __lane_id(), wave = threadIdx.x / 64;
@@ -198,7 +205,17 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
     const int64_t maxlen = (S + NG - 1) / NG;
     const int ntiles = (int)((maxlen + G - 1) / G);
 
-    float *const atom = rep ? rep + (uint64_t)(xcc_id() % (uint32_t)nrep) * rep_stride : out;
+    // Atomic updates of the output: FP32 atomics into out, or, with acc64,
+    // FP64 atomics into an FP64 accumulator that is added into out after the
+    // launch.  The strategies that visit the nonzeros in linearized order
+    // send a hot row's contributions as up to millions of short runs; summed
+    // by FP32 atomics in arbitrary order their rounding error grows like
+    // sqrt(updates) and reaches 1e-4 relative on the skewed tensors, while
+    // FP64 accumulation keeps it at the FP32 rounding of the runs.
+    auto gadd = [&](uint64_t off, float v) {
+        if (acc64) unsafeAtomicAdd(acc64 + off, (double)v);
+        else unsafeAtomicAdd(out + off, v);
+    };
     const int RP = temp_stride(R);
     float *const temp = smem;                                      // staged: Temp rows
     float *const qbuf = smem + (QUEUE ? wave * QR * (RT + 1) : 0);  // atomic: this wave's flush queue
@@ -235,14 +252,24 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
     __syncthreads();
 
     uint32_t cur = kNoRow;
-    float acc[NCOL][VEC];
+    // run accumulator with Kahan compensation: a run of one output row can
+    // hold millions of products (the hottest rows of skewed modes), and a
+    // compensated sum keeps its error at a few units of the last place
+    // whatever the length; the flushed value is acc - cmp
+    float acc[NCOL][VEC], cmp[NCOL][VEC];
 #pragma unroll
     for (int a = 0; a < NCOL; a++)
 #pragma unroll
-        for (int e = 0; e < VEC; e++) acc[a][e] = 0.f;
+        for (int e = 0; e < VEC; e++) acc[a][e] = cmp[a][e] = 0.f;
+
+    // rows with a helper flag (bit 31) belong to this lane group alone:
+    // plain read-modify-write of the output instead of atomics
+    const uint32_t rmask = dec.fbit >= 0 ? ~kOwnBit : 0xffffffffu;
 
     // direct flush: LDS Temp (staged) or global atomics (generic rank)
-    auto flush_direct = [&](uint32_t row) {
+    auto flush_direct = [&](uint32_t raw) {
+        const uint32_t row = raw & rmask;
+        const bool own = dec.fbit >= 0 && (raw & kOwnBit);
 #pragma unroll
         for (int a = 0; a < NCOL; a++) {
             const int col0 = RT ? c * VEC : c + 64 * a;
@@ -250,11 +277,15 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
             if constexpr (kStaged) {
                 float *dst = temp + (uint64_t)(row - lo) * RP + col0;
 #pragma unroll
-                for (int e = 0; e < VEC; e++) atomicAdd(dst + e, acc[a][e]);
-            } else {
-                float *dst = atom + (uint64_t)row * R + col0;
+                for (int e = 0; e < VEC; e++) atomicAdd(dst + e, acc[a][e] - cmp[a][e]);
+            } else if (own) {
+                float *dst = out + (uint64_t)row * R + col0;
 #pragma unroll
-                for (int e = 0; e < VEC; e++) unsafeAtomicAdd(dst + e, acc[a][e]);
+                for (int e = 0; e < VEC; e++) dst[e] += acc[a][e] - cmp[a][e];
+            } else {
+                const uint64_t off = (uint64_t)row * R + col0;
+#pragma unroll
+                for (int e = 0; e < VEC; e++) gadd(off + e, acc[a][e] - cmp[a][e]);
             }
         }
     };
@@ -272,7 +303,8 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
             if (__ballot(dup) == 0) {
                 for (int q0 = 0; q0 < qn; q0 += PER) {
                     const int q = q0 + lane / RT, col = lane % RT;
-                    if (q < qn) unsafeAtomicAdd(atom + (uint64_t)row_at(q) * RT + col, qbuf[q * (RT + 1) + col]);
+                    if (q < qn)
+                        gadd((uint64_t)(row_at(q) & rmask) * RT + col, qbuf[q * (RT + 1) + col]);
                 }
             } else {
                 for (int q0 = 0; q0 < qn; q0 += PER) {
@@ -283,7 +315,7 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
                             float sum = qbuf[q * (RT + 1) + col];
                             for (int q2 = q + 1; q2 < qn && row_at(q2) == row; q2++)
                                 sum += qbuf[q2 * (RT + 1) + col];
-                            unsafeAtomicAdd(atom + (uint64_t)row * RT + col, sum);
+                            gadd((uint64_t)(row & rmask) * RT + col, sum);
                         }
                     }
                 }
@@ -341,6 +373,7 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
             for (int j = 0; j < NO; j++) idx[j] = j < N - 1 ? field(dec.coff[j], dec.cmask[j]) : 0u;
             myrow = field(dec.coff[N - 1], dec.cmask[N - 1]);
         }
+        if (!kStaged && dec.fbit >= 0 && key_bit(key, dec.fbit)) myrow |= kOwnBit;
         if (!ok) myrow = kNoRow;
 
         static_for<G / U>([&](auto kc) {
@@ -391,19 +424,26 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
                 const bool nw = rows[u] != cur;
                 const bool fls = nw && cur != kNoRow;
                 if constexpr (QUEUE) {
-                    // groups whose run ends append (row, accumulator) to the wave's queue
-                    const uint64_t fl = __ballot(fls && c == 0);
+                    // groups whose run ends append (row, accumulator) to the
+                    // wave's queue, except for rows that are this group's
+                    // alone (helper flag), which it adds to the output itself
+                    const bool own = fls && (cur & ~rmask);
+                    const uint64_t fl = __ballot(fls && !own && c == 0);
                     if (nw) {
-                        if (fls) {
+                        if (own) {
+                            float *dst = out + (uint64_t)(cur & rmask) * RT + c * VEC;
+#pragma unroll
+                            for (int q = 0; q < VEC; q++) dst[q] += acc[0][q] - cmp[0][q];
+                        } else if (fls) {
                             const int slot = qn + __builtin_popcountll(fl & ((1ull << (gw * G)) - 1ull));
                             float *e = qbuf + slot * (RT + 1);
 #pragma unroll
-                            for (int q = 0; q < VEC; q++) e[c * VEC + q] = acc[0][q];
+                            for (int q = 0; q < VEC; q++) e[c * VEC + q] = acc[0][q] - cmp[0][q];
                             if (c == 0) e[RT] = __uint_as_float(cur);
                         }
                         cur = rows[u];
 #pragma unroll
-                        for (int e = 0; e < VEC; e++) acc[0][e] = 0.f;
+                        for (int e = 0; e < VEC; e++) acc[0][e] = cmp[0][e] = 0.f;
                     }
                     qn += __builtin_popcountll(fl);
                     if (qn > GPW) drain();  // room for the next item's flushes
@@ -414,23 +454,33 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
 #pragma unroll
                         for (int a = 0; a < NCOL; a++)
 #pragma unroll
-                            for (int e = 0; e < VEC; e++) acc[a][e] = 0.f;
+                            for (int e = 0; e < VEC; e++) acc[a][e] = cmp[a][e] = 0.f;
                     }
                 }
 #pragma unroll
                 for (int a = 0; a < NCOL; a++)
 #pragma unroll
-                    for (int e = 0; e < VEC; e++) acc[a][e] += p[u][a][e];
+                    for (int e = 0; e < VEC; e++) {
+                        const float y = p[u][a][e] - cmp[a][e];
+                        const float tsum = acc[a][e] + y;
+                        cmp[a][e] = (tsum - acc[a][e]) - y;
+                        acc[a][e] = tsum;
+                    }
             }
         });
     }
     if constexpr (QUEUE) {
-        const uint64_t fl = __ballot(cur != kNoRow && c == 0);
-        if (cur != kNoRow) {
+        const bool own = cur != kNoRow && (cur & ~rmask);
+        const uint64_t fl = __ballot(cur != kNoRow && !own && c == 0);
+        if (own) {
+            float *dst = out + (uint64_t)(cur & rmask) * RT + c * VEC;
+#pragma unroll
+            for (int q = 0; q < VEC; q++) dst[q] += acc[0][q] - cmp[0][q];
+        } else if (cur != kNoRow) {
             const int slot = qn + __builtin_popcountll(fl & ((1ull << (gw * G)) - 1ull));
             float *e = qbuf + slot * (RT + 1);
 #pragma unroll
-            for (int q = 0; q < VEC; q++) e[c * VEC + q] = acc[0][q];
+            for (int q = 0; q < VEC; q++) e[c * VEC + q] = acc[0][q] - cmp[0][q];
             if (c == 0) e[RT] = __uint_as_float(cur);
         }
         qn += __builtin_popcountll(fl);
@@ -448,7 +498,7 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
             if (v == 0.f) continue;
             const uint32_t row = lo + (uint32_t)r;
             if (cov[row] == 1u) out[(uint64_t)row * R + col] = v;
-            else unsafeAtomicAdd(atom + (uint64_t)row * R + col, v);
+            else gadd((uint64_t)row * R + col, v);
         }
     }
 }
@@ -465,10 +515,8 @@ struct MtLaunch {
     ModeDec dec;
     const void *ctab;  // byte tables of the compact form (keys <= 64 bits)
     float *out;
-    float *rep;        // replicas (nullptr: atomics straight to out)
-    uint64_t rep_stride;
-    int nrep;
-    const int32_t *list;
+    double *acc64;     // FP64 accumulator of the atomic updates (nullptr: FP32 atomics into out)
+    const int32_t *list;  // segments to process (nullptr: 0 .. n_list-1)
     int n_list;
     int staged;
     int temp_rows;     // LDS Temp rows to reserve (staged launches)
@@ -510,7 +558,7 @@ int launch_mt_cfg(const MtLaunch &a, hipStream_t s) {
         if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute(MaxDynamicSharedMemorySize)");
     }
     kern<<<grid, a.threads, lds, s>>>((const K *)a.keys, a.vals, a.seg, a.ivl, a.cov, a.fac, a.R, a.N, a.mode, a.tab,
-                                      dec, (const K *)a.ctab, (int)(tab_off / 4), a.out, a.rep, a.rep_stride, a.nrep,
+                                      dec, (const K *)a.ctab, (int)(tab_off / 4), a.out, a.acc64,
                                       a.list, a.n_list);
     ALTO_HIP(hipGetLastError());
     return ALTO_OK;
@@ -552,9 +600,22 @@ inline int launch_mt(const MtLaunch &a, int key_bits, int prec, hipStream_t s) {
     return bf ? launch_mt_k128_bf16(a, s) : launch_mt_k128_f32(a, s);
 }
 
-// out[e] += sum of the nrep replicas at e, for e < n
-int launch_replica_reduce(float *out, const float *rep, uint64_t stride, int nrep, uint64_t n, hipStream_t s);
-// number of distinct XCC ids the device reports (0 if it cannot tell)
-int device_xcc_count();
+// Fill everything of *a that does not depend on the segment list: index and
+// values (the segment-local order by `mode` when `sorted`), partition,
+// factor pointers in decode order, LDS staging of small factor matrices, and
+// the workgroup size of an atomic launch.  Allocates nothing.
+int fill_mt_launch(const alto_tensor *t, const void *const *factors, int R, int prec, int mode, bool sorted,
+                   MtLaunch *a);
+// lanes that share one nonzero in the kernels of rank R (see MtCfg)
+inline int mt_group_lanes(int R, int prec) {
+    const bool spec = R == 8 || R == 16 || R == 32 || R == 64;
+    return spec ? R / (prec == ALTO_PREC_BF16 ? 8 : 4) : 64;
+}
+// Checks of alto_mttkrp's arguments that do not depend on the plan.
+int check_mttkrp_args(const alto_tensor *t, const void *const *factors, int R, int prec, int mode,
+                      const float *out);
+
+// out[e] += (float)acc[e], for e < n
+int launch_acc64_finish(float *out, const double *acc, uint64_t n, hipStream_t s);
 
 }  // namespace alto

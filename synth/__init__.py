@@ -155,6 +155,84 @@ def _unique_topup(rec: Recipe, coords, vals):
     raise RuntimeError("could not reach the requested unique count")
 
 
+def planted_cp(dims, rank: int, support, zipf=(), noise: float = 0.1, seed: int = 20210301):
+    """A sparse tensor that is a planted sum of ``rank`` rank-1 terms plus noise.
+
+    Term r lives on a small box: ``support[n]`` distinct rows of mode n, drawn
+    with the mode's Zipf exponent (so hot rows are shared by many terms and
+    the terms overlap), with weights a_n(i, r) in [0.5, 1.5) on a 2^-8 grid.
+    Its nonzeros are the box's cells, valued prod_n a_n(i_n, r); cells that
+    several terms reach hold the sum.  Every value is then multiplied by
+    (1 + noise * z) with z standard normal, so the tensor is exactly rank
+    ``rank`` on its support up to a relative noise of ``noise`` and its best
+    rank-``rank`` fit is about 1 - noise.
+
+    Returns (coords uint32 [N, M], vals float32 [M], factors) with distinct
+    coordinates in row-major order; factors[n] is the dense I_n x rank
+    float64 matrix of the planted weights (zero off the boxes).
+    """
+    N = len(dims)
+    rng = np.random.default_rng(seed)
+    # one stream of draws per mode (one row permutation, so the hot rows are
+    # the same for every term); term r takes the first support[n] distinct
+    # rows of its own stretch of that stream
+    stretch = [max(64, 16 * int(k)) for k in support]
+    draws = []
+    for n in range(N):
+        if int(support[n]) > dims[n]:
+            raise ValueError("support larger than the mode")
+        s = float(zipf[n]) if zipf else 0.0
+        draws.append(mode_coords(seed, n, int(dims[n]), s, stretch[n] * rank))
+    cells = []
+    wts = []
+    planted = [np.zeros((int(d), rank), np.float64) for d in dims]
+    for r in range(rank):
+        rows, w = [], []
+        for n in range(N):
+            k = int(support[n])
+            c = draws[n][r * stretch[n]:(r + 1) * stretch[n]]
+            _, first = np.unique(c, return_index=True)
+            pick = c[np.sort(first)][:k]
+            if pick.size < k:  # a very skewed mode: fill with the lowest unused rows
+                rest = np.setdiff1d(np.arange(dims[n], dtype=np.uint32), pick)[:k - pick.size]
+                pick = np.concatenate([pick, rest])
+            rows.append(pick)
+            w.append((128 + rng.integers(0, 256, size=k)) / 256.0)
+        for n in range(N):
+            planted[n][rows[n], r] = w[n]
+        grid = np.meshgrid(*rows, indexing="ij")
+        val = w[0]
+        for n in range(1, N):
+            val = np.multiply.outer(val, w[n])
+        cells.append(np.stack([g.reshape(-1) for g in grid]))
+        wts.append(val.reshape(-1))
+    coords = np.concatenate(cells, axis=1)
+    vals = np.concatenate(wts)
+    lin = _row_numbers(dims, coords)
+    uniq, inv = np.unique(lin, return_inverse=True)
+    summed = np.zeros(uniq.shape[0], np.float64)
+    np.add.at(summed, inv, vals)
+    first = np.zeros(uniq.shape[0], np.int64)
+    first[inv[::-1]] = np.arange(inv.shape[0])[::-1]
+    coords = np.ascontiguousarray(coords[:, first])
+    summed *= 1.0 + noise * rng.standard_normal(summed.shape[0])
+    return coords, summed.astype(np.float32), planted
+
+
+def planted_start(planted, jitter: float, seed: int = 20210302):
+    """A CP-ALS starting point near planted factors: each entry is
+    planted * (1 + jitter * z) + jitter * u (z standard normal, u uniform in
+    [0, 1)), clipped to [0, 2) and put on the grid k/128, k in 0..255, so
+    that it is exact in bfloat16 and binary32.  Returns float32 matrices."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for f in planted:
+        x = f * (1.0 + jitter * rng.standard_normal(f.shape)) + jitter * rng.random(f.shape)
+        k = np.clip(np.rint(x * 128.0), 0, 255)
+        out.append((k / 128.0).astype(np.float32))
+    return out
+
+
 # Named workloads (shapes and distributions of the benchmark configurations).
 WORKLOADS = {
     # 3-mode uniform tensor, exactly 100k distinct coordinates, R=16

@@ -91,3 +91,38 @@ def test_library_layout_errors():
         alto.layout((4, 0, 2))
     assert e.value.code == alto.E_INVAL
     assert alto.layout((1000, 800, 600), key_bits=128)["key_bits"] == 128
+
+
+def _table1_dims():
+    import json
+    with open(os.path.join(ROOT, "tests", "golden", "table1_tensors.json")) as f:
+        return [(name, tuple(int(round(d)) for d in dims)) for name, dims, _, _ in json.load(f)["tensors"]]
+
+
+@pytest.mark.skipif(not alto.lib_available(), reason="libalto.so not built")
+@pytest.mark.parametrize("name,dims", [(n, tuple(r.dims)) for n, r in __import__("synth").WORKLOADS.items()]
+                         + _table1_dims())
+def test_library_storage_matches_eq1_eq2(name, dims):
+    """Format storage (Section 3.1, Eq. 1 and Eq. 2) as the library lays it
+    out: the index bits per nonzero are Eq. 1's sum of ceil(log2 I_n); the
+    stored word is the smallest of 32, 64 and 128 bits that holds them; and
+    the COO-to-ALTO index ratio in stored words is Eq. 2's ratio with 32-bit
+    words when the ALTO index takes 1, 2 or 4 such words (otherwise the
+    stored word rounds up to the next power of two and the ratio is lower)."""
+    import math
+
+    import oracle
+    got = alto.layout(dims)
+    N = len(dims)
+    B = got["index_bits"]
+    assert B == oracle.storage_bits(dims, 1)
+    W = got["key_bits"]
+    assert W == min(w for w in (32, 64, 128) if w >= B)
+    words = math.ceil(B / 32)
+    eq2 = oracle.compression_ratio(dims, 32)
+    assert eq2 == pytest.approx(N / words)
+    stored = N * 32 / W
+    if words in (1, 2, 4):
+        assert stored == pytest.approx(eq2)
+    else:
+        assert stored < eq2

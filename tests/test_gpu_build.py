@@ -1,5 +1,7 @@
 """GPU format generation vs the oracle, bit for bit: linearized indices,
 their order, coalescing, segment bounds, mode intervals and coverage."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -39,6 +41,12 @@ def test_build_bit_exact(rec, kb, L):
     assert info["masks"] == lay.masks
     assert info["key_bits"] == (kb or lay.W)
     assert info["nnz_in"] == rec.nnz and info["nnz"] == len(olo)
+    # storage (Eq. 1 in stored words) and the device bytes of the tensor proper
+    M, N = info["nnz"], len(rec.dims)
+    assert info["index_bytes"] == M * info["key_bits"] / 8
+    assert info["coo_index_bytes"] == M * N * 4
+    assert info["tensor_bytes"] >= M * (info["key_bits"] / 8 + 4)
+    assert info["order_bytes"] == 0
     keys, gv = t.export_keys()
     glo, ghi = keys_numpy(keys, info["key_bits"])
     assert np.array_equal(glo, olo) and np.array_equal(ghi, ohi)
@@ -163,6 +171,9 @@ def test_mode_order_bit_exact(rec, kb, L):
             assert np.array_equal(gv, ov[perm]), n
         else:
             assert np.allclose(gv, ov[perm], rtol=2e-6, atol=0), n
+    # one reordered copy of index and values per mode, on the current partition
+    info = t.info()
+    assert info["order_bytes"] == len(rec.dims) * M * (info["key_bits"] / 8 + 4)
     t.close()
 
 
@@ -197,4 +208,20 @@ def test_largest_dimension_bit_exact():
         k, _ = t.export_mode_order(n)
         klo, khi = keys_numpy(k, info["key_bits"])
         assert np.array_equal(klo, olo[perm]) and np.array_equal(khi, ohi[perm]), n
+    # an MTTKRP (or CP-ALS) whose output mode has 2^32 rows is refused: row
+    # 2^32-1 would alias the kernels' no-row marker (nothing is launched, so
+    # the small placeholder buffers are never touched)
+    import torch
+    L_ = alto.lib()
+    R = 4
+    small_f = [torch.ones((d, R), dtype=torch.float32, device="cuda") for d in dims[1:]]
+    dummy = torch.zeros(64, dtype=torch.float32, device="cuda")
+    fp = alto._ptr_array([None] + small_f)
+    assert L_.alto_mttkrp(t._h, fp, R, 0, 0, dummy.data_ptr(), None, None) == alto.E_INVAL
+    assert b"2^32" in L_.alto_last_error()
+    lam = torch.zeros(R, dtype=torch.float64, device="cuda")
+    fit = (ctypes.c_double * 1)()
+    fp_all = alto._ptr_array([dummy] + small_f)
+    assert L_.cp_als(t._h, R, 1, 0, fp_all, lam.data_ptr(), fit, None, None) == alto.E_INVAL
+    assert b"2^32" in L_.alto_last_error()
     t.close()

@@ -79,3 +79,21 @@ def test_unique_topup_exact_count():
     assert c.shape == (3, 800) and v.shape == (800,)
     lin = (c[0].astype(int) * 10 + c[1]) * 5 + c[2]
     assert len(np.unique(lin)) == 800
+
+
+def test_planted_cp_is_the_sum_of_its_terms():
+    """With no noise the planted tensor's values are the rank-R model
+    sum_r prod_n A_n(i_n, r) at its (distinct) coordinates."""
+    dims = (300, 200, 50, 9)
+    c, v, P = synth.planted_cp(dims, 6, (7, 5, 4, 3), (1.2, 1.2, 0, 0), noise=0.0, seed=3)
+    lin = ((c[0].astype(np.int64) * dims[1] + c[1]) * dims[2] + c[2]) * dims[3] + c[3]
+    assert np.unique(lin).size == c.shape[1]
+    model = np.ones((c.shape[1], 6))
+    for n in range(4):
+        model *= P[n][c[n]]
+    assert np.allclose(v, model.sum(axis=1), rtol=1e-6)
+    # every term contributes its whole box
+    assert c.shape[1] <= 6 * 7 * 5 * 4 * 3
+    start = synth.planted_start(P, 0.5)
+    for f in start:
+        assert f.dtype == np.float32 and np.all(f * 128 == np.rint(f * 128)) and f.max() < 2
