@@ -191,6 +191,27 @@ int alto_mttkrp(alto_tensor *t, const void *const *factors, int R, int prec, int
                 float *out, const alto_exec *ex, hipStream_t stream);
 
 /*
+ * alto_mttkrp_noalloc — for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same result as alto_mttkrp with
+ * ex = {ALTO_STRATEGY_ATOMIC, 0}, on the tensor's current partition, with
+ * no device allocation and no memset.  Its only scratch memory, the FP64
+ * accumulator of the atomic updates (I_mode x R doubles), is a static
+ * device array of 32 MiB that each GPU the library runs on holds until the
+ * process ends.
+ *   Arguments as for alto_mttkrp.  out is overwritten.
+ *   Errors: ALTO_E_INVAL as alto_mttkrp, and when I_mode * R * 8 bytes
+ *           exceed 32 MiB (I_mode * R <= 4 Mi); ALTO_E_STATE if the tensor
+ *           has no partition.
+ * Every call on one GPU shares that GPU's array and leaves the last call's
+ * partial sums in it: calls that overlap in time on one GPU (on different
+ * streams, or from several threads) race and give wrong results.  Calls
+ * ordered on one stream are safe.  Asynchronous.
+ */
+int alto_mttkrp_noalloc(const alto_tensor *t, const void *const *factors, int R, int prec, int mode,
+                        float *out, hipStream_t stream);
+
+/*
  * cp_als — `iters` iterations of CP-ALS (Section 2.2): for each mode n in
  * turn, M_n = MTTKRP_n; V = Hadamard product of the Grams A_m^T A_m, m != n
  * (FP64); A_n = M_n V^{-1}, V inverted by Gauss-Jordan elimination whose

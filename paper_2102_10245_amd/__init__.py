@@ -25,7 +25,7 @@ STRATEGY_NAME = {v: k for k, v in STRATEGY.items()}
 
 # Names the C ABI exports (include/alto.h).
 EXPORTS = (
-    "alto_build", "alto_info", "alto_partition", "alto_mttkrp", "cp_als", "alto_select",
+    "alto_build", "alto_info", "alto_partition", "alto_mttkrp", "alto_mttkrp_noalloc", "cp_als", "alto_select",
     "alto_selector_load", "alto_selector_features", "alto_mlp_forward", "alto_mlp_backward",
     "alto_mlp_adam", "alto_export_keys", "alto_export_mode_order", "alto_export_partition", "alto_export_coverage",
     "alto_round_bf16", "alto_transpose", "alto_append", "alto_export_flags", "alto_free", "alto_last_error", "alto_device_compute_units", "alto_layout",
@@ -81,6 +81,7 @@ def lib():
     L.alto_layout.argtypes = [vp, i32, i32, ctypes.POINTER(_Info)]
     L.alto_partition.argtypes = [vp, i32, vp]
     L.alto_mttkrp.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp]
+    L.alto_mttkrp_noalloc.argtypes = [vp, vp, i32, i32, i32, vp, vp]
     L.cp_als.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp]
     L.alto_select.argtypes = [vp, i32, i32, i32, ctypes.POINTER(_Exec)]
     L.alto_selector_load.argtypes = [vp, ctypes.c_size_t]
@@ -255,6 +256,24 @@ class AltoTensor:
         ex = _Exec(STRATEGY[strategy], num_segments)
         fp = _ptr_array([f if n != mode else None for n, f in enumerate(factors)])
         _check(self._lib.alto_mttkrp(self._h, fp, R, prec, mode, _ptr(out), ctypes.byref(ex), _stream(stream)))
+        return out
+
+    def mttkrp_noalloc(self, factors, mode: int, out, stream=None):
+        """alto_mttkrp_noalloc: atomic-update MTTKRP on the current partition with
+        no device allocation; `out` (float32 CUDA tensor [I_mode, R]) is required."""
+        torch = _torch()
+        inf = self.info()
+        if not 0 <= mode < inf["N"] or len(factors) != inf["N"]:
+            raise ValueError("mode out of range or wrong number of factors")
+        R = next(f.shape[1] for f in factors if f is not None)
+        for n, f in enumerate(factors):
+            if n != mode:
+                _check_factor(f, inf["dims"][n], R)
+        prec = _prec_of([f for n, f in enumerate(factors) if n != mode])
+        if out.dtype != torch.float32 or tuple(out.shape) != (inf["dims"][mode], R) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 tensor of shape (I_mode, R)")
+        fp = _ptr_array([f if n != mode else None for n, f in enumerate(factors)])
+        _check(self._lib.alto_mttkrp_noalloc(self._h, fp, R, prec, mode, _ptr(out), _stream(stream)))
         return out
 
     def cp_als(self, factors, iters: int, strategy: str = "auto", num_segments: int = 0, stream=None):

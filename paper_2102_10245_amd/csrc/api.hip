@@ -759,6 +759,8 @@ int alto_build(const uint32_t *const *coords, const float *vals, int64_t nnz, co
 #undef ALTO_TRY
     rc = select_partition(t, o.num_segments, s);
     if (rc) return fail(rc);
+    rc = noalloc_prepare_device();
+    if (rc) return fail(rc);
     *out = t;
     return ALTO_OK;
 }

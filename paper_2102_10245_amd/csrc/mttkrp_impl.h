@@ -617,5 +617,7 @@ int check_mttkrp_args(const alto_tensor *t, const void *const *factors, int R, i
 
 // out[e] += (float)acc[e], for e < n
 int launch_acc64_finish(float *out, const double *acc, uint64_t n, hipStream_t s);
+// set-up of alto_mttkrp_noalloc on the current device
+int noalloc_prepare_device();
 
 }  // namespace alto

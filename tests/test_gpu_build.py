@@ -219,6 +219,7 @@ def test_largest_dimension_bit_exact():
     fp = alto._ptr_array([None] + small_f)
     assert L_.alto_mttkrp(t._h, fp, R, 0, 0, dummy.data_ptr(), None, None) == alto.E_INVAL
     assert b"2^32" in L_.alto_last_error()
+    assert L_.alto_mttkrp_noalloc(t._h, fp, R, 0, 0, dummy.data_ptr(), None) == alto.E_INVAL
     lam = torch.zeros(R, dtype=torch.float64, device="cuda")
     fit = (ctypes.c_double * 1)()
     fp_all = alto._ptr_array([dummy] + small_f)
