@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle CPU time")
     ap.add_argument("--mttkrp-only", action="store_true",
                     help="only per-mode MTTKRP repetitions of the chosen plan (for counter collection)")
+    ap.add_argument("--prec", default="f32", choices=("f32", "bf16"),
+                    help="factor precision of the --mttkrp-only repetitions")
     ap.add_argument("--format", action="store_true",
                     help="format generation and storage on every workload: alto_build time and index "
                          "bytes vs COO (prints its own JSON line instead of the benchmark line)")
@@ -178,7 +180,8 @@ def main():
         torch.cuda.synchronize()
         del a, b
         t = alto.AltoTensor.build(c_dev, v_dev, rec.dims)
-        per_mode = time_modes(alto, torch, t, init_f32, R, N, args.reps, "f32", "auto")
+        fs = init_f32 if args.prec == "f32" else init_bf16
+        per_mode = time_modes(alto, torch, t, fs, R, N, args.reps, args.prec, "auto")
         print(json.dumps({"mttkrp_only": per_mode}))
         t.close()
         return

@@ -200,6 +200,15 @@ int build_mode_order(alto_tensor *t, int mode, hipStream_t s) {
         (void)hipFree(ov);
         return rc;
     }
+    if (t->key_bits <= 64) {
+        rc = launch_compact_keys(t->key_bits, ok, n, t->ctab, s);
+        if (rc) {
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(ok);
+            (void)hipFree(ov);
+            return rc;
+        }
+    }
     P.okeys[mode] = ok;
     P.ovals[mode] = ov;
     return ALTO_OK;
@@ -479,6 +488,7 @@ int fill_mt_launch(const alto_tensor *t, const void *const *factors, int R, int 
     a.mode = mode;
     a.tab = t->tab;
     a.ctab = t->ctab;
+    a.dec.compact = sorted && t->key_bits <= 64;
     a.wide = false;
     const uint64_t fs = prec == ALTO_PREC_BF16 ? 2u : 4u;
     for (int m = 0; m < t->N; m++)
@@ -517,49 +527,27 @@ int fill_mt_launch(const alto_tensor *t, const void *const *factors, int R, int 
     return ALTO_OK;
 }
 
-// Helper flags of `mode` for the current partition cut into NG lane groups
-// per segment (the unit that walks its nonzeros in order): flag set iff the
-// nonzero's row lies in the mode interval of no other lane group's range
-// (Section 3.2's coverage, computed over those ranges).  Computed once per
-// (partition, NG) and kept in the index's spare bit.
+// Helper flags of `mode` (Section 3.3) for the current partition cut into
+// NG lane groups per segment (the unit that walks its nonzeros in order):
+// flag set iff every nonzero of the row lies in the same lane-group range.
+// Only for modes of limited fiber reuse (nnz / I_mode <= 4, where the reuse
+// rule picks atomics); computed once per (partition, NG) and kept in the
+// index's spare bit.
 int ensure_flags(alto_tensor *t, int mode, int NG, hipStream_t s) {
     Partition &P = *t->part;
     if (t->flag_bit[mode] < 0 || t->nnz == 0 || P.L == 0) return ALTO_OK;
+    if ((double)t->nnz > 4.0 * (double)t->dims[mode]) return ALTO_OK;
     if (t->flag_L[mode] == P.L && t->flag_NG[mode] == NG) return ALTO_OK;
-    const int64_t Lm = (int64_t)P.L * NG;
-    if (Lm > 0x7fffffff) return ALTO_OK;
-    std::vector<int64_t> h(Lm + 1);
-    for (int l = 0; l < P.L; l++) {
-        const int64_t sb = P.h_seg[l], S = P.h_seg[l + 1] - sb;
-        for (int g = 0; g < NG; g++) h[(int64_t)l * NG + g] = sb + (S * g) / NG;
-    }
-    h[Lm] = t->nnz;
-    int64_t *d_seg = nullptr;
-    uint32_t *d_ivl = nullptr, *d_cov = nullptr;
-    auto done = [&](int rc) {
-        (void)hipStreamSynchronize(s);
-        (void)hipFree(d_seg);
-        (void)hipFree(d_ivl);
-        (void)hipFree(d_cov);
-        return rc;
-    };
-    hipError_t e = hipMalloc(&d_seg, sizeof(int64_t) * (Lm + 1));
-    if (e == hipSuccess) e = hipMalloc(&d_ivl, sizeof(uint32_t) * Lm * t->N * 2);
-    if (e == hipSuccess) e = hipMalloc(&d_cov, sizeof(uint32_t) * t->dims[mode]);
-    if (e == hipSuccess) e = hipMemcpyAsync(d_seg, h.data(), sizeof(int64_t) * (Lm + 1), hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return done(hip_error(e, "helper flags"));
-    int rc = launch_intervals(t->key_bits, t->keys, d_seg, (int)Lm, t->tab, t->ctab, d_ivl, s);
-    if (rc) return done(rc);
-    rc = ensure_workspace(t, coverage_scratch(t->dims[mode]));
-    if (rc) return done(rc);
-    rc = coverage(t->N, (int)Lm, d_ivl, mode, t->dims[mode], d_cov, t->ws, t->ws_bytes, s);
-    if (rc) return done(rc);
-    rc = launch_set_flags(t->key_bits, t->keys, t->nnz, t->tab, t->ctab, mode, d_cov, t->flag_bit[mode], s);
-    if (rc) return done(rc);
+    if ((uint64_t)P.L * (uint64_t)NG >= 0xfffffffeull) return ALTO_OK;
+    int rc = ensure_workspace(t, sizeof(uint32_t) * t->dims[mode]);
+    if (rc) return rc;
+    rc = launch_owner_flags(t->key_bits, t->keys, P.d_seg, P.L, NG, t->tab, t->ctab, mode, (uint32_t *)t->ws,
+                            t->dims[mode], t->flag_bit[mode], s);
+    if (rc) return rc;
     t->flags_in_keys = true;
     t->flag_L[mode] = P.L;
     t->flag_NG[mode] = NG;
-    return done(ALTO_OK);
+    return ALTO_OK;
 }
 
 int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int prec, int mode, float *out,
@@ -588,7 +576,11 @@ int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int p
     // their atomic updates in FP64 (see mttkrp_k); the segment-local order
     // makes one FP32 atomic per (segment, row) run, directly into out
     const bool fp64 = !sorted;
-    const size_t acc_bytes = fp64 ? sizeof(double) * outn : 0;
+    // per-XCD copies when the output is small: its few lines would otherwise
+    // take the atomics of the whole GPU
+    const int nxcc = fp64 ? device_xcc_count() : 1;
+    const int nacc = nxcc > 1 && (uint64_t)nxcc * outn * sizeof(double) <= ((uint64_t)64 << 20) ? nxcc : 1;
+    const size_t acc_bytes = fp64 ? sizeof(double) * outn * nacc : 0;
     if (fp64 && t->acc64_bytes < acc_bytes) {
         if (t->acc64) ALTO_HIP(hipFree(t->acc64));
         t->acc64 = nullptr;
@@ -602,6 +594,8 @@ int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int p
     if (rc) return rc;
     a.out = out;
     a.acc64 = fp64 ? t->acc64 : nullptr;
+    a.acc_stride = outn;
+    a.nacc = nacc;
     const int atomic_wg = a.threads;
     // helper flags for the launches that update the output with atomics on
     // the linearized order (ALTO_HELPER_FLAGS=0 turns them off)
@@ -637,7 +631,7 @@ int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int p
     }
     rc = run(p, sl->n_atomic, 0, 0);
     if (rc) return rc;
-    if (fp64) return launch_acc64_finish(out, t->acc64, outn, s);
+    if (fp64) return launch_acc64_finish(out, t->acc64, outn, nacc, outn, s);
     return ALTO_OK;
 }
 
@@ -886,7 +880,10 @@ int alto_export_mode_order(alto_tensor *t, int mode, void *keys_out, float *vals
     if (rc) return rc;
     const Partition &P = *t->part;
     if (keys_out) {
-        if (t->flags_in_keys) {
+        if (t->key_bits <= 64) {
+            rc = launch_expand_keys(t->key_bits, P.okeys[mode], t->nnz, t->tab, keys_out, s);
+            if (rc) return rc;
+        } else if (t->flags_in_keys) {
             rc = launch_mask_keys(t->key_bits, P.okeys[mode], t->nnz, t->B, keys_out, s);
             if (rc) return rc;
         } else {

@@ -702,22 +702,38 @@ __device__ __forceinline__ u128 with_bit<u128>(u128 k, int pos, bool v) {
     return k;
 }
 
-template <typename K>
-__global__ __launch_bounds__(kThreads) void set_flags_k(K *__restrict__ keys, int64_t n, RunTable tab,
-                                                         const K *__restrict__ ctab, int mode,
-                                                         const uint32_t *__restrict__ cov, int fbit) {
+// Exact helper flags.  Segment l (one workgroup) of S nonzeros is cut
+// into NG lane-group ranges as the MTTKRP kernel cuts it: offset o of the
+// segment belongs to group floor(((o + 1) * NG - 1) / S).  Every nonzero
+// claims its row for its range (l * NG + g); a row claimed by two ranges
+// becomes kConflict.  A nonzero is then internal iff its row's owner is its
+// own range.
+constexpr uint32_t kOwnerEmpty = 0xffffffffu, kOwnerConflict = 0xfffffffeu;
+
+template <typename K, bool kMark>
+__global__ __launch_bounds__(kThreads) void owner_k(K *__restrict__ keys, const int64_t *__restrict__ seg, int NG,
+                                                    RunTable tab, const K *__restrict__ ctab, int mode,
+                                                    uint32_t *__restrict__ owner, int fbit) {
     constexpr int kTab = byte_table_entries(8 * (int)sizeof(K));
     __shared__ K lt[kTab > 0 ? kTab : 1];
     if constexpr (kTab > 0) {
         for (int q = threadIdx.x; q < kTab; q += kThreads) lt[q] = ctab[q];
         __syncthreads();
     }
-    for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < n; x += (int64_t)gridDim.x * kThreads) {
-        const K key = keys[x];
+    const int l = blockIdx.x;
+    const int64_t sb = seg[l], S = seg[l + 1] - sb;
+    for (int64_t o = threadIdx.x; o < S; o += kThreads) {
+        const K key = keys[sb + o];
         uint32_t row;
         if constexpr (kTab > 0) row = (uint32_t)(compact_index(key, lt) >> tab.coff[mode]) & tab.cmask[mode];
         else row = extract_mode(key, tab, mode);
-        keys[x] = with_bit(key, fbit, cov[row] == 1u);
+        const uint32_t chunk = (uint32_t)l * (uint32_t)NG + (uint32_t)(((o + 1) * NG - 1) / S);
+        if constexpr (kMark) {
+            keys[sb + o] = with_bit(key, fbit, owner[row] == chunk);
+        } else {
+            const uint32_t prev = atomicCAS(&owner[row], kOwnerEmpty, chunk);
+            if (prev != kOwnerEmpty && prev != chunk) atomicExch(&owner[row], kOwnerConflict);
+        }
     }
 }
 
@@ -752,7 +768,60 @@ __global__ __launch_bounds__(kThreads) void get_flags_k(const K *__restrict__ ke
     }
 }
 
+// The segment-local mode orders keep their index words in compact form
+// (each mode's coordinate in a contiguous bit field, as the byte tables
+// assemble it), so the MTTKRP over them needs no table lookups.
+template <typename K>
+__global__ __launch_bounds__(kThreads) void compact_keys_k(K *__restrict__ keys, int64_t n, const K *__restrict__ ctab) {
+    constexpr int kTab = byte_table_entries(8 * (int)sizeof(K));
+    __shared__ K lt[kTab];
+    for (int q = threadIdx.x; q < kTab; q += kThreads) lt[q] = ctab[q];
+    __syncthreads();
+    for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < n; x += (int64_t)gridDim.x * kThreads)
+        keys[x] = compact_index(keys[x], lt);
+}
+
+// compact form -> linearized index (the bit-level gather again, from the fields)
+template <typename K>
+__global__ __launch_bounds__(kThreads) void expand_keys_k(const K *__restrict__ cw, int64_t n, RunTable tab,
+                                                           K *__restrict__ out) {
+    for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < n; x += (int64_t)gridDim.x * kThreads) {
+        const K c = cw[x];
+        K k = 0;
+        for (int m = 0; m < tab.N; m++) {
+            const uint32_t v = (uint32_t)(c >> tab.coff[m]) & tab.cmask[m];
+            for (int q = 0; q < tab.nruns[m]; q++) {
+                const uint32_t r = tab.run[m][q];
+                const int len = run_len(r);
+                const uint32_t bits = (v >> run_cpos(r)) & (uint32_t)((1ull << len) - 1);
+                KeyOps<K>::deposit(k, bits, run_kpos(r));
+            }
+        }
+        out[x] = k;
+    }
+}
+
 // ------------------------------------------------------------ launchers
+int launch_compact_keys(int key_bits, void *keys, int64_t n, const void *ctab, hipStream_t s) {
+    if (n <= 0) return ALTO_OK;
+    if (key_bits > 64 || !ctab) return set_error(ALTO_E_INVAL, "internal: compact keys need byte tables");
+    const unsigned g = std::min<unsigned>(grid_for(n, kThreads * 4), 4096);
+    if (key_bits == 32) compact_keys_k<uint32_t><<<g, kThreads, 0, s>>>((uint32_t *)keys, n, (const uint32_t *)ctab);
+    else compact_keys_k<uint64_t><<<g, kThreads, 0, s>>>((uint64_t *)keys, n, (const uint64_t *)ctab);
+    ALTO_HIP(hipGetLastError());
+    return ALTO_OK;
+}
+
+int launch_expand_keys(int key_bits, const void *cw, int64_t n, const RunTable &tab, void *out, hipStream_t s) {
+    if (n <= 0) return ALTO_OK;
+    if (key_bits > 64) return set_error(ALTO_E_INVAL, "internal: no compact form for 128-bit keys");
+    const unsigned g = std::min<unsigned>(grid_for(n, kThreads * 4), 4096);
+    if (key_bits == 32) expand_keys_k<uint32_t><<<g, kThreads, 0, s>>>((const uint32_t *)cw, n, tab, (uint32_t *)out);
+    else expand_keys_k<uint64_t><<<g, kThreads, 0, s>>>((const uint64_t *)cw, n, tab, (uint64_t *)out);
+    ALTO_HIP(hipGetLastError());
+    return ALTO_OK;
+}
+
 int launch_get_flags(int key_bits, const void *keys, int64_t n, int fbit, uint8_t *out, hipStream_t s) {
     if (n <= 0) return ALTO_OK;
     const unsigned g = std::min<unsigned>(grid_for(n, kThreads * 4), 4096);
@@ -763,17 +832,21 @@ int launch_get_flags(int key_bits, const void *keys, int64_t n, int fbit, uint8_
     return ALTO_OK;
 }
 
-int launch_set_flags(int key_bits, void *keys, int64_t n, const RunTable &tab, const void *ctab, int mode,
-                     const uint32_t *cov, int fbit, hipStream_t s) {
-    if (n <= 0) return ALTO_OK;
+int launch_owner_flags(int key_bits, void *keys, const int64_t *seg, int L, int NG, const RunTable &tab,
+                       const void *ctab, int mode, uint32_t *owner, uint64_t dim, int fbit, hipStream_t s) {
+    if (L <= 0) return ALTO_OK;
     if (key_bits <= 64 && !ctab) return set_error(ALTO_E_INVAL, "internal: missing byte tables");
-    const unsigned g = std::min<unsigned>(grid_for(n, kThreads * 4), 4096);
-    if (key_bits == 32)
-        set_flags_k<uint32_t><<<g, kThreads, 0, s>>>((uint32_t *)keys, n, tab, (const uint32_t *)ctab, mode, cov, fbit);
-    else if (key_bits == 64)
-        set_flags_k<uint64_t><<<g, kThreads, 0, s>>>((uint64_t *)keys, n, tab, (const uint64_t *)ctab, mode, cov, fbit);
-    else set_flags_k<u128><<<g, kThreads, 0, s>>>((u128 *)keys, n, tab, nullptr, mode, cov, fbit);
-    ALTO_HIP(hipGetLastError());
+    ALTO_HIP(hipMemsetAsync(owner, 0xff, sizeof(uint32_t) * dim, s));
+    for (int pass = 0; pass < 2; pass++) {
+#define ALTO_OWN(K, CT)                                                                                        \
+    (pass == 0 ? owner_k<K, false><<<L, kThreads, 0, s>>>((K *)keys, seg, NG, tab, (const K *)(CT), mode, owner, fbit) \
+               : owner_k<K, true><<<L, kThreads, 0, s>>>((K *)keys, seg, NG, tab, (const K *)(CT), mode, owner, fbit))
+        if (key_bits == 32) ALTO_OWN(uint32_t, ctab);
+        else if (key_bits == 64) ALTO_OWN(uint64_t, ctab);
+        else ALTO_OWN(u128, nullptr);
+#undef ALTO_OWN
+        ALTO_HIP(hipGetLastError());
+    }
     return ALTO_OK;
 }
 

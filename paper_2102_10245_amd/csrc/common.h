@@ -159,7 +159,7 @@ struct Partition {
     std::map<uint64_t, SegLists> lists;
     // segment-local mode orders: index and values reordered inside each
     // segment by one mode's coordinate
-    void *okeys[kMaxModes] = {};
+    void *okeys[kMaxModes] = {};  // compact words for keys of at most 64 bits
     float *ovals[kMaxModes] = {};
     Partition() = default;
     Partition(const Partition &) = delete;
@@ -247,9 +247,14 @@ int coverage(int N, int L, const uint32_t *d_ivl, int mode, uint64_t dim, uint32
              size_t scratch_bytes, hipStream_t s);
 size_t coverage_scratch(uint64_t dim);
 int launch_sumsq(const float *vals, int64_t n, double *out, hipStream_t s);
-// helper flags: bit `fbit` of every index := cov[row along mode] == 1
-int launch_set_flags(int key_bits, void *keys, int64_t n, const RunTable &tab, const void *ctab, int mode,
-                     const uint32_t *cov, int fbit, hipStream_t s);
+// helper flags: bit `fbit` of every index := its row along `mode` is
+// touched by its own lane-group range only (segments from seg, NG ranges
+// each; owner: scratch of dim uint32)
+int launch_owner_flags(int key_bits, void *keys, const int64_t *seg, int L, int NG, const RunTable &tab,
+                       const void *ctab, int mode, uint32_t *owner, uint64_t dim, int fbit, hipStream_t s);
+// index words -> compact words in place, and back (keys of at most 64 bits)
+int launch_compact_keys(int key_bits, void *keys, int64_t n, const void *ctab, hipStream_t s);
+int launch_expand_keys(int key_bits, const void *cw, int64_t n, const RunTable &tab, void *out, hipStream_t s);
 // out[x] = bit fbit of index x
 int launch_get_flags(int key_bits, const void *keys, int64_t n, int fbit, uint8_t *out, hipStream_t s);
 // out = keys with every bit at or above B cleared (out may equal keys)

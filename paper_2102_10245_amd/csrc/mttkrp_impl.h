@@ -49,7 +49,8 @@ struct FactorPtrs {
 // modes with bit j of smask have their whole factor matrix (sbytes[j] bytes)
 // copied to LDS at byte offset soff[j] and are gathered from there.
 struct ModeDec {
-    int fbit;  // index bit of the output mode's helper flag (-1: no flags)
+    int fbit;     // index bit of the output mode's helper flag (-1: no flags)
+    int compact;  // the index words are already compact words (keys of at most 64 bits)
     int om[kMaxModes];
     uint32_t coff[kMaxModes];
     uint32_t cmask[kMaxModes];
@@ -84,6 +85,11 @@ __device__ __forceinline__ uint32_t group_bcast(uint32_t x) {
 }
 
 constexpr uint32_t kNoRow = 0xffffffffu;
+
+__device__ __forceinline__ uint32_t xcc_id() {
+    // hwreg(HW_REG_XCC_ID, 0, 4): id 20, offset 0, 4 bits
+    return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 0xfu;
+}
 // with helper flags the output row carries its flag in bit 31 (rows < 2^31 - 1)
 constexpr uint32_t kOwnBit = 0x80000000u;
 
@@ -176,7 +182,7 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
     const K *__restrict__ keys, const float *__restrict__ vals, const int64_t *__restrict__ seg,
     const uint32_t *__restrict__ ivl, const uint32_t *__restrict__ cov, FactorPtrs fac, int R_rt, int N_rt, int mode,
     RunTable tab, ModeDec dec, const K *__restrict__ ctab, int ctab_off, float *__restrict__ out,
-    double *__restrict__ acc64, const int32_t *__restrict__ seg_list, int n_list) {
+    double *__restrict__ acc64_base, uint64_t acc_stride, int nacc, const int32_t *__restrict__ seg_list, int n_list) {
     using C = MtCfg<NT, RT, FT>;
     constexpr int VEC = C::kVec, G = C::kG, GPW = C::kGPW, NM = C::kNMax, NCOL = C::kCols, U = C::kU;
     constexpr int NO = NM - 1;  // other modes
@@ -212,6 +218,9 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
     // by FP32 atomics in arbitrary order their rounding error grows like
     // sqrt(updates) and reaches 1e-4 relative on the skewed tensors, while
     // FP64 accumulation keeps it at the FP32 rounding of the runs.
+    // with nacc > 1 each XCD adds into a copy of its own (chosen by the XCC
+    // id register), which spreads the atomics on a small output's few lines
+    double *const acc64 = acc64_base ? acc64_base + (uint64_t)(xcc_id() % (uint32_t)nacc) * acc_stride : nullptr;
     auto gadd = [&](uint64_t off, float v) {
         if (acc64) unsafeAtomicAdd(acc64 + off, (double)v);
         else unsafeAtomicAdd(out + off, v);
@@ -229,10 +238,12 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
     }
     K *const ltab = reinterpret_cast<K *>(smem + ctab_off);
     if constexpr (kTab > 0) {
-        constexpr int n16 = kTab * (int)sizeof(K) / 16;
-        const uint4 *src = reinterpret_cast<const uint4 *>(ctab);
-        uint4 *dst = reinterpret_cast<uint4 *>(ltab);
-        for (int q = threadIdx.x; q < n16; q += blockDim.x) dst[q] = src[q];
+        if (!dec.compact) {
+            constexpr int n16 = kTab * (int)sizeof(K) / 16;
+            const uint4 *src = reinterpret_cast<const uint4 *>(ctab);
+            uint4 *dst = reinterpret_cast<uint4 *>(ltab);
+            for (int q = threadIdx.x; q < n16; q += blockDim.x) dst[q] = src[q];
+        }
     } else {
         // 128-bit indices: tbytes128 tables of 256 {lo, hi} entries
         const int n16 = tab.tbytes128 * 256;
@@ -345,7 +356,8 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
         uint32_t idx[NO];
         uint32_t myrow;
         if constexpr (kTab > 0) {
-            const K cw = compact_index(key, ltab);  // key is 0 (all coordinates 0) past the end
+            // key is 0 (all coordinates 0) past the end
+            const K cw = dec.compact ? key : compact_index(key, ltab);
 #pragma unroll
             for (int j = 0; j < NO; j++) idx[j] = j < N - 1 ? (uint32_t)(cw >> dec.coff[j]) & dec.cmask[j] : 0u;
             myrow = (uint32_t)(cw >> dec.coff[N - 1]) & dec.cmask[N - 1];
@@ -516,6 +528,8 @@ struct MtLaunch {
     const void *ctab;  // byte tables of the compact form (keys <= 64 bits)
     float *out;
     double *acc64;     // FP64 accumulator of the atomic updates (nullptr: FP32 atomics into out)
+    uint64_t acc_stride;  // elements between its per-XCD copies
+    int nacc;             // number of copies (>= 1)
     const int32_t *list;  // segments to process (nullptr: 0 .. n_list-1)
     int n_list;
     int staged;
@@ -530,7 +544,7 @@ int launch_mt_cfg(const MtLaunch &a, hipStream_t s) {
     const size_t main_lds = a.staged ? (size_t)a.temp_rows * temp_stride(a.R) * 4
                                      : (size_t)mt_queue_bytes<NT, RT, FT>(a.threads);
     const size_t tab_off = (main_lds + 15) / 16 * 16;
-    const size_t tab_bytes = sizeof(K) <= 8 ? (size_t)byte_table_entries(8 * (int)sizeof(K)) * sizeof(K)
+    const size_t tab_bytes = sizeof(K) <= 8 ? (a.dec.compact ? 0 : (size_t)byte_table_entries(8 * (int)sizeof(K)) * sizeof(K))
                                             : (size_t)a.tab.tbytes128 * 256 * 16;
     size_t lds = tab_off + tab_bytes;
     ModeDec dec = a.dec;
@@ -558,7 +572,8 @@ int launch_mt_cfg(const MtLaunch &a, hipStream_t s) {
         if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute(MaxDynamicSharedMemorySize)");
     }
     kern<<<grid, a.threads, lds, s>>>((const K *)a.keys, a.vals, a.seg, a.ivl, a.cov, a.fac, a.R, a.N, a.mode, a.tab,
-                                      dec, (const K *)a.ctab, (int)(tab_off / 4), a.out, a.acc64,
+                                      dec, (const K *)a.ctab, (int)(tab_off / 4), a.out, a.acc64, a.acc_stride,
+                                      a.nacc < 1 ? 1 : a.nacc,
                                       a.list, a.n_list);
     ALTO_HIP(hipGetLastError());
     return ALTO_OK;
@@ -615,8 +630,10 @@ inline int mt_group_lanes(int R, int prec) {
 int check_mttkrp_args(const alto_tensor *t, const void *const *factors, int R, int prec, int mode,
                       const float *out);
 
-// out[e] += (float)acc[e], for e < n
-int launch_acc64_finish(float *out, const double *acc, uint64_t n, hipStream_t s);
+// out[e] += (float)(sum over the nacc copies of acc at e), for e < n
+int launch_acc64_finish(float *out, const double *acc, uint64_t stride, int nacc, uint64_t n, hipStream_t s);
+// number of distinct XCC ids the device reports (probed once per device)
+int device_xcc_count();
 // set-up of alto_mttkrp_noalloc on the current device
 int noalloc_prepare_device();
 

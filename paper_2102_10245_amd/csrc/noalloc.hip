@@ -90,11 +90,13 @@ extern "C" int alto_mttkrp_noalloc(const alto_tensor *t, const void *const *fact
     if (rc) return rc;
     a.out = out;
     a.acc64 = acc;
+    a.acc_stride = outn;
+    a.nacc = 1;
     a.list = nullptr;  // every segment, in order
     a.n_list = t->part->L;
     a.staged = 0;
     a.temp_rows = 0;
     rc = launch_mt(a, t->key_bits, prec, s);
     if (rc) return rc;
-    return launch_acc64_finish(out, acc, outn, s);
+    return launch_acc64_finish(out, acc, outn, 1, outn, s);
 }
