@@ -263,15 +263,11 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
     __syncthreads();
 
     uint32_t cur = kNoRow;
-    // run accumulator with Kahan compensation: a run of one output row can
-    // hold millions of products (the hottest rows of skewed modes), and a
-    // compensated sum keeps its error at a few units of the last place
-    // whatever the length; the flushed value is acc - cmp
-    float acc[NCOL][VEC], cmp[NCOL][VEC];
+    float acc[NCOL][VEC];
 #pragma unroll
     for (int a = 0; a < NCOL; a++)
 #pragma unroll
-        for (int e = 0; e < VEC; e++) acc[a][e] = cmp[a][e] = 0.f;
+        for (int e = 0; e < VEC; e++) acc[a][e] = 0.f;
 
     // rows with a helper flag (bit 31) belong to this lane group alone:
     // plain read-modify-write of the output instead of atomics
@@ -288,15 +284,15 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
             if constexpr (kStaged) {
                 float *dst = temp + (uint64_t)(row - lo) * RP + col0;
 #pragma unroll
-                for (int e = 0; e < VEC; e++) atomicAdd(dst + e, acc[a][e] - cmp[a][e]);
+                for (int e = 0; e < VEC; e++) atomicAdd(dst + e, acc[a][e]);
             } else if (own) {
                 float *dst = out + (uint64_t)row * R + col0;
 #pragma unroll
-                for (int e = 0; e < VEC; e++) dst[e] += acc[a][e] - cmp[a][e];
+                for (int e = 0; e < VEC; e++) dst[e] += acc[a][e];
             } else {
                 const uint64_t off = (uint64_t)row * R + col0;
 #pragma unroll
-                for (int e = 0; e < VEC; e++) gadd(off + e, acc[a][e] - cmp[a][e]);
+                for (int e = 0; e < VEC; e++) gadd(off + e, acc[a][e]);
             }
         }
     };
@@ -445,17 +441,17 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
                         if (own) {
                             float *dst = out + (uint64_t)(cur & rmask) * RT + c * VEC;
 #pragma unroll
-                            for (int q = 0; q < VEC; q++) dst[q] += acc[0][q] - cmp[0][q];
+                            for (int q = 0; q < VEC; q++) dst[q] += acc[0][q];
                         } else if (fls) {
                             const int slot = qn + __builtin_popcountll(fl & ((1ull << (gw * G)) - 1ull));
                             float *e = qbuf + slot * (RT + 1);
 #pragma unroll
-                            for (int q = 0; q < VEC; q++) e[c * VEC + q] = acc[0][q] - cmp[0][q];
+                            for (int q = 0; q < VEC; q++) e[c * VEC + q] = acc[0][q];
                             if (c == 0) e[RT] = __uint_as_float(cur);
                         }
                         cur = rows[u];
 #pragma unroll
-                        for (int e = 0; e < VEC; e++) acc[0][e] = cmp[0][e] = 0.f;
+                        for (int e = 0; e < VEC; e++) acc[0][e] = 0.f;
                     }
                     qn += __builtin_popcountll(fl);
                     if (qn > GPW) drain();  // room for the next item's flushes
@@ -466,18 +462,13 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
 #pragma unroll
                         for (int a = 0; a < NCOL; a++)
 #pragma unroll
-                            for (int e = 0; e < VEC; e++) acc[a][e] = cmp[a][e] = 0.f;
+                            for (int e = 0; e < VEC; e++) acc[a][e] = 0.f;
                     }
                 }
 #pragma unroll
                 for (int a = 0; a < NCOL; a++)
 #pragma unroll
-                    for (int e = 0; e < VEC; e++) {
-                        const float y = p[u][a][e] - cmp[a][e];
-                        const float tsum = acc[a][e] + y;
-                        cmp[a][e] = (tsum - acc[a][e]) - y;
-                        acc[a][e] = tsum;
-                    }
+                    for (int e = 0; e < VEC; e++) acc[a][e] += p[u][a][e];
             }
         });
     }
@@ -487,12 +478,12 @@ __global__ __launch_bounds__(1024) void mttkrp_k(
         if (own) {
             float *dst = out + (uint64_t)(cur & rmask) * RT + c * VEC;
 #pragma unroll
-            for (int q = 0; q < VEC; q++) dst[q] += acc[0][q] - cmp[0][q];
+            for (int q = 0; q < VEC; q++) dst[q] += acc[0][q];
         } else if (cur != kNoRow) {
             const int slot = qn + __builtin_popcountll(fl & ((1ull << (gw * G)) - 1ull));
             float *e = qbuf + slot * (RT + 1);
 #pragma unroll
-            for (int q = 0; q < VEC; q++) e[c * VEC + q] = acc[0][q] - cmp[0][q];
+            for (int q = 0; q < VEC; q++) e[c * VEC + q] = acc[0][q];
             if (c == 0) e[RT] = __uint_as_float(cur);
         }
         qn += __builtin_popcountll(fl);

@@ -161,7 +161,7 @@ def test_full_size_sampled_rows(name, R, kind, strategies):
     # the output as millions of short runs; the library adds those with FP64
     # atomics (FP32 atomics measured up to 8e-4 here, a random walk of
     # roundings of the running sum).  The segment-local order sums every
-    # (segment, row) run in registers with compensation before one FP32
+    # (segment, row) run in registers before one FP32
     # atomic per run.  Measured worst rows: 7e-8 and 1.5e-6.
     tol = {"atomic": TOL, "staged": TOL, "sorted": TOL}
     for mode in range(N):
