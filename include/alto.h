@@ -365,6 +365,26 @@ const char *alto_last_error(void);
 /* alto_device_compute_units — compute units of the current device (host query). */
 int alto_device_compute_units(void);
 
+/*
+ * Kernel timing, for measurement.  While enabled, every MTTKRP the library
+ * runs (alto_mttkrp, and those inside alto_cp_als and the selector's timing
+ * of candidates) records a pair of HIP events on its stream: the first just
+ * before its first MTTKRP kernel, the second after its last one (the FP64
+ * accumulator finish included).  The output clear and the plan set-up before
+ * the kernels lie outside the pair, so the pair measures what a kernel trace
+ * reports for the MTTKRP kernels of the call.
+ *
+ * alto_timing_enable — enable != 0 starts recording, 0 stops it (pairs
+ *   already recorded stay until read).  Always ALTO_OK.
+ * alto_timing_read — waits for every recorded pair and writes the sum of
+ *   their elapsed times (milliseconds) to *ms_total and their number to
+ *   *calls (host pointers), then clears the record.  ALTO_E_INVAL for a null
+ *   pointer; a HIP error if an event cannot be read.
+ * The record is per process, shared by all threads and streams.
+ */
+int alto_timing_enable(int enable);
+int alto_timing_read(double *ms_total, int64_t *calls);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,6 +29,7 @@ EXPORTS = (
     "alto_selector_load", "alto_selector_features", "alto_mlp_forward", "alto_mlp_backward",
     "alto_mlp_adam", "alto_export_keys", "alto_export_mode_order", "alto_export_partition", "alto_export_coverage",
     "alto_round_bf16", "alto_transpose", "alto_append", "alto_export_flags", "alto_free", "alto_last_error", "alto_device_compute_units", "alto_layout",
+    "alto_timing_enable", "alto_timing_read",
 )
 
 
@@ -102,6 +103,8 @@ def lib():
     L.alto_free.restype = None
     L.alto_last_error.restype = ctypes.c_char_p
     L.alto_device_compute_units.restype = i32
+    L.alto_timing_enable.argtypes = [i32]
+    L.alto_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     _lib = L
     return L
 
@@ -423,6 +426,20 @@ def load_default_selector() -> bool:
 
 def compute_units() -> int:
     return int(lib().alto_device_compute_units())
+
+
+def timing_enable(enable: bool = True):
+    """Start (or stop) recording an event pair around the MTTKRP kernels of
+    every MTTKRP the library runs (measurement only)."""
+    _check(lib().alto_timing_enable(1 if enable else 0))
+
+
+def timing_read():
+    """(total milliseconds, number of MTTKRPs) recorded since the last read."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(lib().alto_timing_read(ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 # ------------------------------------------------------------------ selector network kernels

@@ -5,6 +5,8 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <utility>
+#include <vector>
 
 #include "common.h"
 #include "mttkrp_impl.h"
@@ -550,6 +552,45 @@ int ensure_flags(alto_tensor *t, int mode, int NG, hipStream_t s) {
     return ALTO_OK;
 }
 
+// Kernel timing for measurement (alto_timing_enable / alto_timing_read): an
+// event pair per MTTKRP around its kernels, on the launch stream.
+namespace {
+using EventPair = std::pair<hipEvent_t, hipEvent_t>;
+std::mutex g_tm_mu;
+bool g_tm_on = false;
+std::vector<EventPair> g_tm_pending, g_tm_free;
+
+struct CallTimer {
+    EventPair ev{nullptr, nullptr};
+    bool active = false;
+    int begin(hipStream_t s) {
+        {
+            std::lock_guard<std::mutex> lk(g_tm_mu);
+            if (!g_tm_on) return ALTO_OK;
+            if (!g_tm_free.empty()) {
+                ev = g_tm_free.back();
+                g_tm_free.pop_back();
+            }
+        }
+        if (!ev.first) {
+            ALTO_HIP(hipEventCreate(&ev.first));
+            ALTO_HIP(hipEventCreate(&ev.second));
+        }
+        ALTO_HIP(hipEventRecord(ev.first, s));
+        active = true;
+        return ALTO_OK;
+    }
+    int end(hipStream_t s) {
+        if (!active) return ALTO_OK;
+        active = false;
+        ALTO_HIP(hipEventRecord(ev.second, s));
+        std::lock_guard<std::mutex> lk(g_tm_mu);
+        g_tm_pending.push_back(ev);
+        return ALTO_OK;
+    }
+};
+}  // namespace
+
 int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int prec, int mode, float *out,
                         const alto_exec *ex, hipStream_t s) {
     int rc = check_mttkrp_args(t, factors, R, prec, mode, out);
@@ -576,10 +617,11 @@ int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int p
     // their atomic updates in FP64 (see mttkrp_k); the segment-local order
     // makes one FP32 atomic per (segment, row) run, directly into out
     const bool fp64 = !sorted;
-    // per-XCD copies when the output is small: its few lines would otherwise
-    // take the atomics of the whole GPU
+    // per-XCD copies unless the output is large: the hot lines of a small or
+    // skewed output would otherwise take the atomics of the whole GPU.  The
+    // copies cost one clear and one read each (at most 0.1 ms at 256 MiB)
     const int nxcc = fp64 ? device_xcc_count() : 1;
-    const int nacc = nxcc > 1 && (uint64_t)nxcc * outn * sizeof(double) <= ((uint64_t)64 << 20) ? nxcc : 1;
+    const int nacc = nxcc > 1 && (uint64_t)nxcc * outn * sizeof(double) <= ((uint64_t)256 << 20) ? nxcc : 1;
     const size_t acc_bytes = fp64 ? sizeof(double) * outn * nacc : 0;
     if (fp64 && t->acc64_bytes < acc_bytes) {
         if (t->acc64) ALTO_HIP(hipFree(t->acc64));
@@ -624,6 +666,9 @@ int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int p
                 sl->n_bucket[2], sl->w_bucket[0], sl->w_bucket[1], sl->w_bucket[2], (int)fp64, a.dec.fbit >= 0);
     const int32_t *p = sl->d;
     const int32_t *bucket_p = p + sl->n_atomic;
+    CallTimer timer;
+    rc = timer.begin(s);
+    if (rc) return rc;
     for (int b = 0; b < SegLists::kBuckets; b++) {
         rc = run(bucket_p, sl->n_bucket[b], 1, sl->w_bucket[b]);
         if (rc) return rc;
@@ -631,8 +676,11 @@ int plan_and_run_mttkrp(alto_tensor *t, const void *const *factors, int R, int p
     }
     rc = run(p, sl->n_atomic, 0, 0);
     if (rc) return rc;
-    if (fp64) return launch_acc64_finish(out, t->acc64, outn, nacc, outn, s);
-    return ALTO_OK;
+    if (fp64) {
+        rc = launch_acc64_finish(out, t->acc64, outn, nacc, outn, s);
+        if (rc) return rc;
+    }
+    return timer.end(s);
 }
 
 }  // namespace alto
@@ -642,6 +690,38 @@ using namespace alto;
 extern "C" {
 
 const char *alto_last_error(void) { return alto::g_err.c_str(); }
+
+int alto_timing_enable(int enable) {
+    std::lock_guard<std::mutex> lk(g_tm_mu);
+    g_tm_on = enable != 0;
+    return ALTO_OK;
+}
+
+int alto_timing_read(double *ms_total, int64_t *calls) {
+    if (!ms_total || !calls) return set_error(ALTO_E_INVAL, "null output pointer");
+    std::vector<EventPair> pend;
+    {
+        std::lock_guard<std::mutex> lk(g_tm_mu);
+        pend.swap(g_tm_pending);
+    }
+    double tot = 0.0;
+    int rc = ALTO_OK;
+    for (const EventPair &p : pend) {
+        if (rc) break;
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(p.second);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.first, p.second);
+        if (e != hipSuccess) rc = hip_error(e, "alto_timing_read");
+        tot += ms;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tm_mu);
+        g_tm_free.insert(g_tm_free.end(), pend.begin(), pend.end());
+    }
+    *ms_total = tot;
+    *calls = (int64_t)pend.size();
+    return rc;
+}
 
 int alto_device_compute_units(void) { return cu_count(); }
 

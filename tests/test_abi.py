@@ -64,6 +64,9 @@ def test_argument_errors_without_device_work():
     assert L.alto_mlp_adam(0, None, None, None, None, 0.1, 0.9, 0.99, 1e-8, 1, None) == alto.E_INVAL
     assert L.alto_round_bf16(None, None, -1, None) == alto.E_INVAL
     L.alto_free(None)
+    # kernel timing: null outputs; an empty record reads as nothing
+    assert L.alto_timing_read(None, None) == alto.E_INVAL
+    assert alto.timing_read() == (0.0, 0)
 
 
 @pytest.mark.skipif(not alto.lib_available(), reason="libalto.so not built")

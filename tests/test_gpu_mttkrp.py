@@ -78,6 +78,36 @@ def test_repartition_through_exec():
     t.close()
 
 
+def test_kernel_timing_records_every_call():
+    """alto_timing_enable / alto_timing_read: one event pair per MTTKRP while
+    enabled, none otherwise; the kernels take no longer than the whole calls
+    (torch events around them on the same stream)."""
+    import torch
+    rec = small("zipf4_1Mx100kx10kx500_150M", 200_000)
+    coords, vals = synth.coo(rec)
+    c, v = to_dev(coords, vals)
+    t = alto.AltoTensor.build(c, v, rec.dims)
+    fd = factors_dev(synth.factors(3, rec.dims, 32))
+    for st in ("sorted", "atomic", "staged"):
+        out = t.mttkrp(fd, 3, strategy=st)  # plans, orders and flags first
+        alto.timing_read()
+        alto.timing_enable(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(4):
+            t.mttkrp(fd, 3, out=out, strategy=st)
+        e1.record()
+        alto.timing_enable(False)
+        t.mttkrp(fd, 3, out=out, strategy=st)  # not recorded
+        torch.cuda.synchronize()
+        ms, n = alto.timing_read()
+        print(st, "kernels", ms, "calls", e0.elapsed_time(e1), flush=True)
+        assert n == 4
+        assert 0.0 < ms <= e0.elapsed_time(e1) * 1.001
+        assert alto.timing_read() == (0.0, 0)
+    t.close()
+
+
 def test_empty_tensor_gives_zero_output():
     torch = pytest.importorskip("torch")
     c = torch.zeros((3, 0), dtype=torch.int32, device="cuda")
