@@ -140,9 +140,9 @@ int select_plan(const alto_tensor *t, int mode, int R, int prec, alto_exec *out,
 std::vector<alto_exec> selector_candidates() {
     std::lock_guard<std::mutex> lk(g_sel_mu);
     std::vector<alto_exec> c;
-    const int nL = g_sel.loaded ? g_sel.nL : 5;
+    const int nL = g_sel.loaded ? g_sel.nL : 7;
     const int S = g_sel.loaded ? g_sel.K / g_sel.nL : 3;
-    static const int kDefaultLs[5] = {512, 1024, 2048, 4096, 8192};
+    static const int kDefaultLs[7] = {256, 512, 1024, 2048, 4096, 8192, 16384};
     for (int st = 0; st < S; st++)
         for (int q = 0; q < nL; q++)
             c.push_back(alto_exec{kOrder[st], g_sel.loaded ? (int)g_sel.Ls[q] : kDefaultLs[q]});

@@ -37,7 +37,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 STRATEGIES = ("atomic", "staged", "sorted")
-LS = (512, 1024, 2048, 4096, 8192)
+LS = (256, 512, 1024, 2048, 4096, 8192, 16384)
 K = len(STRATEGIES) * len(LS)
 F, H = 12, 64
 N_TRAIN, N_TOTAL = 400, 500
@@ -77,14 +77,18 @@ def heuristic_index(feat_reuse_log2):
 
 
 # ------------------------------------------------------------------ corpus
-def corpus(first, count, out, reps=2):
+def corpus(first, count, out, reps=2, max_seconds=None):
     import torch
     import paper_2102_10245_amd as alto
     import synth
     alto.selector_load(None)
     dev = torch.device("cuda", 0)
+    start = time.time()
     with open(out, "a") as fo:
         for i in range(first, first + count):
+            if max_seconds is not None and time.time() - start > max_seconds:
+                print(f"[corpus] stopping before tensor {i}: {max_seconds} s spent", flush=True)
+                break
             t0 = time.time()
             rec, prec = recipe(i)
             coords, vals = synth.coo(rec)
@@ -253,6 +257,8 @@ def evaluate(rows, w, mean, scale, n_val=80):
         t_sel = Tm[np.arange(len(rs)), choice]
         t_heur = np.array([Tm[q, heuristic_index(X[q, 2])] for q in range(len(rs))])
         t_fixed = Tm[:, fixed]
+        # the library's own strategy at its default segment count (8 per CU)
+        t_sorted_default = Tm[:, STRATEGIES.index("sorted") * len(LS) + LS.index(2048)]
         ratio = t_sel / t_best
         out["summary"][split] = {
             "samples": len(rs),
@@ -261,6 +267,7 @@ def evaluate(rows, w, mean, scale, n_val=80):
             "gain_over_reuse_rule_geomean": float(np.exp(np.mean(np.log(t_heur / t_sel)))),
             "reuse_rule_regret_geomean": float(np.exp(np.mean(np.log(t_heur / t_best))) - 1),
             "gain_over_best_fixed_geomean": float(np.exp(np.mean(np.log(t_fixed / t_sel)))),
+            "gain_over_sorted_default_L_geomean": float(np.exp(np.mean(np.log(t_sorted_default / t_sel)))),
             "best_fixed_regret_geomean": float(np.exp(np.mean(np.log(t_fixed / t_best))) - 1),
             "total_ms_selected": float(t_sel.sum()), "total_ms_best": float(t_best.sum()),
             "total_ms_reuse_rule": float(t_heur.sum()), "total_ms_best_fixed": float(t_fixed.sum()),
@@ -275,13 +282,14 @@ def main():
     c.add_argument("--first", type=int, default=0)
     c.add_argument("--count", type=int, default=N_TOTAL)
     c.add_argument("--out", default=CORPUS)
+    c.add_argument("--max-seconds", type=float, default=None, help="stop before the next tensor after this long")
     t = sub.add_parser("train")
     t.add_argument("--corpus", nargs="+", default=[CORPUS])
     t.add_argument("--steps", type=int, default=1500)
     t.add_argument("--out-dir", default=HERE)
     a = ap.parse_args()
     if a.cmd == "corpus":
-        corpus(a.first, a.count, a.out)
+        corpus(a.first, a.count, a.out, max_seconds=a.max_seconds)
     else:
         train(a.corpus, steps=a.steps, out_dir=a.out_dir)
 
