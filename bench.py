@@ -53,6 +53,9 @@ def parse():
                     help="only per-mode MTTKRP repetitions of the chosen plan (for counter collection)")
     ap.add_argument("--prec", default="f32", choices=("f32", "bf16"),
                     help="factor precision of the --mttkrp-only repetitions")
+    ap.add_argument("--plan", default="auto",
+                    help="plan of the --mttkrp-only repetitions: auto (the library's choice) or "
+                         "STRATEGY:L, e.g. sorted:512, one plan for every mode")
     ap.add_argument("--format", action="store_true",
                     help="format generation and storage on every workload: alto_build time and index "
                          "bytes vs COO (prints its own JSON line instead of the benchmark line)")
@@ -181,7 +184,8 @@ def main():
         del a, b
         t = alto.AltoTensor.build(c_dev, v_dev, rec.dims)
         fs = init_f32 if args.prec == "f32" else init_bf16
-        per_mode = time_modes(alto, torch, t, fs, R, N, args.reps, args.prec, "auto")
+        st, _, L = args.plan.partition(":")
+        per_mode = time_modes(alto, torch, t, fs, R, N, args.reps, args.prec, st, int(L or 0))
         print(json.dumps({"mttkrp_only": per_mode}))
         t.close()
         return
@@ -226,8 +230,10 @@ def main():
     t = alto.AltoTensor.build(c_dev, v_dev, rec.dims)
     per_mode = {}
     for prec, fs in (("f32", init_f32), ("bf16", init_bf16)):
+        # the fixed strategies at the library's default segment count (8 per CU)
         for st in ("auto", "atomic", "staged", "sorted"):
-            per_mode[f"{st}_{prec}"] = time_modes(alto, torch, t, fs, R, N, args.reps, prec, st)
+            per_mode[f"{st}_{prec}"] = time_modes(alto, torch, t, fs, R, N, args.reps, prec, st,
+                                                  0 if st == "auto" else 8 * alto.compute_units())
     kb = t.info()["key_bits"]
     t.close()
 
@@ -310,21 +316,21 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def time_modes(alto, torch, t, factors, R, N, reps, prec, strategy):
+def time_modes(alto, torch, t, factors, R, N, reps, prec, strategy, num_segments=0):
     info = t.info()
     M = info["nnz"]
     fb = 4 if prec == "f32" else 2
     res = []
     for mode in range(N):
         out = torch.empty((info["dims"][mode], R), dtype=torch.float32, device=factors[0].device)
-        strat, L = t.select(mode, R, prec) if strategy == "auto" else (strategy, 0)
-        t.mttkrp(factors, mode, out=out, strategy=strategy)  # warmup (plans, orders)
+        strat, L = t.select(mode, R, prec) if strategy == "auto" else (strategy, num_segments)
+        t.mttkrp(factors, mode, out=out, strategy=strategy, num_segments=num_segments)  # warmup (plans, orders)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         alto.timing_read()
         alto.timing_enable(True)
         e0.record()
         for _ in range(reps):
-            t.mttkrp(factors, mode, out=out, strategy=strategy)
+            t.mttkrp(factors, mode, out=out, strategy=strategy, num_segments=num_segments)
         e1.record()
         torch.cuda.synchronize()
         alto.timing_enable(False)

@@ -379,6 +379,37 @@ int ensure_workspace(alto_tensor *t, size_t bytes) {
     return ALTO_OK;
 }
 
+// Selector features from row counts: at most 2^20 evenly spaced nonzeros
+// of the tensor order, counted per mode into min(I_n, 2^24)
+// buckets (rows of larger modes fold onto them by hashing).
+int compute_row_features(alto_tensor *t, hipStream_t s) {
+    for (int n = 0; n < t->N; n++) t->row_hot[n] = t->row_distinct[n] = 0.f;
+    if (t->nnz == 0) return ALTO_OK;
+    const int64_t S = std::min<int64_t>(t->nnz, (int64_t)1 << 20);
+    uint64_t nb_max = 0;
+    for (int n = 0; n < t->N; n++) nb_max = std::max<uint64_t>(nb_max, std::min<uint64_t>(t->dims[n], 1u << 24));
+    int rc = ensure_workspace(t, sizeof(uint32_t) * (nb_max + 2 * kMaxModes));
+    if (rc) return rc;
+    uint32_t *res = (uint32_t *)t->ws;
+    uint32_t *cnt = res + 2 * kMaxModes;
+    ALTO_HIP(hipMemsetAsync(res, 0, sizeof(uint32_t) * 2 * kMaxModes, s));
+    for (int n = 0; n < t->N; n++) {
+        const uint32_t nb = (uint32_t)std::min<uint64_t>(t->dims[n], 1u << 24);
+        ALTO_HIP(hipMemsetAsync(cnt, 0, sizeof(uint32_t) * nb, s));
+        rc = launch_row_sample(t->key_bits, t->keys, S, t->nnz, t->tab, t->ctab, n, t->dims[n], nb, cnt, res + 2 * n, s);
+        if (rc) return rc;
+    }
+    uint32_t h[2 * kMaxModes];
+    ALTO_HIP(hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, s));
+    ALTO_HIP(hipStreamSynchronize(s));
+    for (int n = 0; n < t->N; n++) {
+        const double nb = (double)std::min<uint64_t>(t->dims[n], 1u << 24);
+        t->row_hot[n] = (float)std::log2(std::max(1.0, (double)h[2 * n]) * (double)t->dims[n] / (double)S);
+        t->row_distinct[n] = (float)std::log2(std::max(1.0, (double)h[2 * n + 1]) / std::min((double)S, nb));
+    }
+    return ALTO_OK;
+}
+
 // Exhaustive timing: run every candidate (strategy, L) once to build its
 // plan and order, time a second run with events on the stream, keep the
 // fastest.  The selector's fallback outside its training range.
@@ -491,6 +522,7 @@ int fill_mt_launch(const alto_tensor *t, const void *const *factors, int R, int 
     a.tab = t->tab;
     a.ctab = t->ctab;
     a.dec.compact = sorted && t->key_bits <= 64;
+    a.ordered = sorted;
     a.wide = false;
     const uint64_t fs = prec == ALTO_PREC_BF16 ? 2u : 4u;
     for (int m = 0; m < t->N; m++)
@@ -832,6 +864,8 @@ int alto_build(const uint32_t *const *coords, const float *vals, int64_t nnz, co
     }
 #undef ALTO_TRY
     rc = select_partition(t, o.num_segments, s);
+    if (rc) return fail(rc);
+    rc = compute_row_features(t, s);
     if (rc) return fail(rc);
     rc = noalloc_prepare_device();
     if (rc) return fail(rc);

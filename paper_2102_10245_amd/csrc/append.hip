@@ -202,5 +202,7 @@ extern "C" int alto_append(alto_tensor *t, const uint32_t *const *coords, const 
     t->spare.clear();
     t->tuned.clear();
     rc = make_partition(t, L, s);
+    if (rc) return done(rc);
+    rc = compute_row_features(t, s);
     return done(rc);
 }

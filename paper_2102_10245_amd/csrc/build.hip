@@ -801,7 +801,72 @@ __global__ __launch_bounds__(kThreads) void expand_keys_k(const K *__restrict__ 
     }
 }
 
+// ------------------------------------------------------------ row statistics
+// Row counts of one mode over a strided sample of the nonzeros (selector
+// features: how hot the hottest row is, how many rows the sample touches).
+template <typename K>
+__global__ __launch_bounds__(kThreads) void row_sample_k(const K *__restrict__ keys, int64_t S, int64_t M,
+                                                         RunTable tab, const K *__restrict__ ctab, int mode,
+                                                         uint32_t nb, bool hashed, uint32_t *__restrict__ cnt) {
+    constexpr int kTab = byte_table_entries(8 * (int)sizeof(K));
+    __shared__ K ltab[kTab > 0 ? kTab : 1];
+    if constexpr (kTab > 0) {
+        for (int q = threadIdx.x; q < kTab; q += kThreads) ltab[q] = ctab[q];
+        __syncthreads();
+    }
+    for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < S; x += (int64_t)gridDim.x * kThreads) {
+        const K key = keys[x * M / S];  // S evenly spaced nonzeros
+        uint32_t r;
+        if constexpr (kTab > 0) r = (uint32_t)(compact_index(key, ltab) >> tab.coff[mode]) & tab.cmask[mode];
+        else r = extract_mode(key, tab, mode);
+        // Fibonacci hashing folds large modes onto nb buckets
+        const uint32_t b = hashed ? (uint32_t)(((uint64_t)(r * 2654435769u) * nb) >> 32) : r;
+        atomicAdd(&cnt[b], 1u);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void count_stats_k(const uint32_t *__restrict__ cnt, uint32_t n,
+                                                          uint32_t *__restrict__ res) {
+    uint32_t mx = 0, nz = 0;
+    for (uint32_t x = blockIdx.x * kThreads + threadIdx.x; x < n; x += gridDim.x * kThreads) {
+        const uint32_t c = cnt[x];
+        mx = max(mx, c);
+        nz += c != 0u;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        mx = max(mx, (uint32_t)__shfl_xor((int)mx, off));
+        nz += (uint32_t)__shfl_xor((int)nz, off);
+    }
+    if (__lane_id() == 0) {
+        atomicMax(&res[0], mx);
+        atomicAdd(&res[1], nz);
+    }
+}
+
 // ------------------------------------------------------------ launchers
+int launch_row_sample(int key_bits, const void *keys, int64_t S, int64_t M, const RunTable &tab,
+                      const void *ctab, int mode, uint64_t dim, uint32_t nb, uint32_t *cnt, uint32_t *res,
+                      hipStream_t s) {
+    if (S <= 0 || nb == 0) return ALTO_OK;
+    if (key_bits <= 64 && !ctab) return set_error(ALTO_E_INVAL, "internal: missing byte tables");
+    const bool hashed = (uint64_t)nb < dim;
+    const unsigned g = std::min<unsigned>(grid_for(S, kThreads * 4), 2048);
+    if (key_bits == 32)
+        row_sample_k<uint32_t><<<g, kThreads, 0, s>>>((const uint32_t *)keys, S, M, tab, (const uint32_t *)ctab,
+                                                       mode, nb, hashed, cnt);
+    else if (key_bits == 64)
+        row_sample_k<uint64_t><<<g, kThreads, 0, s>>>((const uint64_t *)keys, S, M, tab, (const uint64_t *)ctab,
+                                                       mode, nb, hashed, cnt);
+    else
+        row_sample_k<u128><<<g, kThreads, 0, s>>>((const u128 *)keys, S, M, tab, nullptr, mode, nb, hashed, cnt);
+    ALTO_HIP(hipGetLastError());
+    const unsigned g2 = std::min<unsigned>(grid_for(nb, kThreads * 4), 2048);
+    count_stats_k<<<g2, kThreads, 0, s>>>(cnt, nb, res);
+    ALTO_HIP(hipGetLastError());
+    return ALTO_OK;
+}
+
 int launch_compact_keys(int key_bits, void *keys, int64_t n, const void *ctab, hipStream_t s) {
     if (n <= 0) return ALTO_OK;
     if (key_bits > 64 || !ctab) return set_error(ALTO_E_INVAL, "internal: compact keys need byte tables");

@@ -218,6 +218,12 @@ struct alto_tensor {
     int flag_L[alto::kMaxModes] = {};
     int flag_NG[alto::kMaxModes] = {};
     bool flags_in_keys = false;  // some flag bit may be set in keys
+    // selector features from the row counts of evenly spaced nonzeros (set
+    // by alto_build and alto_append): per mode, log2 of the
+    // hottest row's count over the count a uniform mode would give, and log2
+    // of the fraction of distinct rows in the sample
+    float row_hot[alto::kMaxModes] = {};
+    float row_distinct[alto::kMaxModes] = {};
 };
 
 namespace alto {
@@ -257,6 +263,15 @@ int launch_compact_keys(int key_bits, void *keys, int64_t n, const void *ctab, h
 int launch_expand_keys(int key_bits, const void *cw, int64_t n, const RunTable &tab, void *out, hipStream_t s);
 // out[x] = bit fbit of index x
 int launch_get_flags(int key_bits, const void *keys, int64_t n, int fbit, uint8_t *out, hipStream_t s);
+// cnt[b] += 1 for every sampled nonzero (indices floor(k * M / S), k < S)
+// whose mode-`mode` row r maps to bucket b = r (nb >= dims[mode]) or a hash
+// of r (nb < dims[mode]); then res[0] = max(res[0], max cnt) and res[1] +=
+// the number of nonzero buckets (res zeroed by the caller)
+int launch_row_sample(int key_bits, const void *keys, int64_t S, int64_t M, const RunTable &tab,
+                      const void *ctab, int mode, uint64_t dim, uint32_t nb, uint32_t *cnt, uint32_t *res,
+                      hipStream_t s);
+// the row features of every mode (t->row_hot, t->row_distinct); synchronizes s
+int compute_row_features(alto_tensor *t, hipStream_t s);
 // out = keys with every bit at or above B cleared (out may equal keys)
 int launch_mask_keys(int key_bits, const void *keys, int64_t n, int B, void *out, hipStream_t s);
 // segment-local order by `mode` (scratch: seg_order_scratch bytes)

@@ -191,7 +191,10 @@ __host__ __device__ constexpr int mt_queue_bytes(int threads) {
 }
 
 
-template <typename K, int NT, int RT, typename FT, bool kStaged, bool kWide>
+// kOrdered changes no code: launches over a segment-local mode order get a
+// kernel symbol of their own, so that a kernel trace separates them from
+// launches over the linearized order.
+template <typename K, int NT, int RT, typename FT, bool kStaged, bool kWide, bool kOrdered = false>
 __global__ __launch_bounds__(1024) void mttkrp_k(
     const K *__restrict__ keys, const float *__restrict__ vals, const int64_t *__restrict__ seg,
     const uint32_t *__restrict__ ivl, const uint32_t *__restrict__ cov, FactorPtrs fac, int R_rt, int N_rt, int mode,
@@ -541,6 +544,7 @@ struct MtLaunch {
     int temp_rows;     // LDS Temp rows to reserve (staged launches)
     int threads;       // workgroup size (multiple of 64, <= 1024)
     bool wide;         // some gathered factor matrix spans more than 4 GiB
+    bool ordered;      // keys and values are a segment-local mode order
 };
 
 template <typename K, int NT, int RT, typename FT>
@@ -570,7 +574,9 @@ int launch_mt_cfg(const MtLaunch &a, hipStream_t s) {
         kern = a.staged ? mttkrp_k<K, NT, RT, FT, true, true> : mttkrp_k<K, NT, RT, FT, false, true>;
     } else {
         kern = a.staged ? (a.wide ? mttkrp_k<K, NT, RT, FT, true, true> : mttkrp_k<K, NT, RT, FT, true, false>)
-                        : (a.wide ? mttkrp_k<K, NT, RT, FT, false, true> : mttkrp_k<K, NT, RT, FT, false, false>);
+                        : (a.wide ? mttkrp_k<K, NT, RT, FT, false, true>
+                                  : (a.ordered ? mttkrp_k<K, NT, RT, FT, false, false, true>
+                                               : mttkrp_k<K, NT, RT, FT, false, false>));
     }
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

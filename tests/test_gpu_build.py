@@ -226,3 +226,41 @@ def test_largest_dimension_bit_exact():
     assert L_.cp_als(t._h, R, 1, 0, fp_all, lam.data_ptr(), fit, None, None) == alto.E_INVAL
     assert b"2^32" in L_.alto_last_error()
     t.close()
+
+
+ROW_FEATURE_CASES = [
+    small("zipf4_1Mx100kx10kx500_150M", 300_000),                                  # 64-bit index
+    small("zipf5_10Mx5Mx2Mx100kx1k_200M", 150_000),                                # 128-bit index
+    synth.Recipe("tall_mode", (1 << 25, 100, 50), 60_000, (1.2, 0, 0.5), seed=11),  # 2^25 rows: hashed buckets
+    synth.Recipe("many", (600, 400, 100), 3_000_000, (1.0, 0.3, 0), seed=12),       # over 2^20 nonzeros: a spaced sample
+]
+
+
+@pytest.mark.parametrize("rec", ROW_FEATURE_CASES, ids=[r.name for r in ROW_FEATURE_CASES])
+def test_row_skew_features_match_a_host_count(rec):
+    """The selector's two skew features (alto_selector_features 12 and 13):
+    row counts of the nonzeros floor(k * M / S), k < S = min(M, 2^20), of the
+    ordered tensor, modes over 2^24 rows folded onto 2^24 buckets by
+    the multiplicative hash; counted here on the host from the oracle's
+    ordered tensor."""
+    coords, vals = synth.coo(rec)
+    c, v = to_dev(coords, vals)
+    t = alto.AltoTensor.build(c, v, rec.dims)
+    (lo, hi), _, lay, _ = oracle_alto(rec.dims, coords, vals)
+    M = len(lo)
+    assert t.info()["nnz"] == M
+    S = min(M, 1 << 20)
+    idx = np.arange(S, dtype=np.int64) * M // S
+    rows = oracle.decode(lay, (lo[idx], hi[idx]))
+    for mode, I in enumerate(rec.dims):
+        nb = min(I, 1 << 24)
+        r = rows[mode].astype(np.uint64)
+        b = r if nb == I else (((r * np.uint64(2654435769)) & np.uint64(0xffffffff)) * np.uint64(nb)) >> np.uint64(32)
+        cnt = np.bincount(b.astype(np.int64), minlength=1)
+        hot = np.log2(max(1, cnt.max()) * I / S)
+        distinct = np.log2(max(1, np.count_nonzero(cnt)) / min(S, nb))
+        f = t.selector_features(mode, 16, "f32")
+        print(rec.name, mode, f[12], hot, f[13], distinct, flush=True)
+        assert f[12] == pytest.approx(hot, rel=1e-6, abs=1e-6)
+        assert f[13] == pytest.approx(distinct, rel=1e-6, abs=1e-6)
+    t.close()
