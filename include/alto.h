@@ -56,7 +56,8 @@ typedef enum {
 /* Conflict resolution for the MTTKRP output (Section 3.3, Algorithm 2). */
 typedef enum {
     ALTO_STRATEGY_AUTO = 0,    /* the plan alto_select describes (network, timing fallback, reuse rule) */
-    ALTO_STRATEGY_ATOMIC = 1,  /* every partial result goes to the output with FP32 atomics */
+    ALTO_STRATEGY_ATOMIC = 1,  /* every partial result goes to the output by atomics, summed in an
+                                  FP64 accumulator that is added into the output after the launch */
     ALTO_STRATEGY_STAGED = 2,  /* per-segment partials in on-chip local memory over the segment's
                                   mode interval, then merged into the output; segments whose
                                   interval does not fit fall back to atomics */

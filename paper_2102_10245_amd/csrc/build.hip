@@ -814,14 +814,33 @@ __global__ __launch_bounds__(kThreads) void row_sample_k(const K *__restrict__ k
         for (int q = threadIdx.x; q < kTab; q += kThreads) ltab[q] = ctab[q];
         __syncthreads();
     }
-    for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < S; x += (int64_t)gridDim.x * kThreads) {
-        const K key = keys[x * M / S];  // S evenly spaced nonzeros
-        uint32_t r;
-        if constexpr (kTab > 0) r = (uint32_t)(compact_index(key, ltab) >> tab.coff[mode]) & tab.cmask[mode];
-        else r = extract_mode(key, tab, mode);
-        // Fibonacci hashing folds large modes onto nb buckets
-        const uint32_t b = hashed ? (uint32_t)(((uint64_t)(r * 2654435769u) * nb) >> 32) : r;
-        atomicAdd(&cnt[b], 1u);
+    const int lane = __lane_id();
+    // every wave runs the same number of rounds (the ballots below need
+    // the whole wave); lanes past S take no part
+    const int64_t step = (int64_t)gridDim.x * kThreads;
+    for (int64_t x0 = (int64_t)blockIdx.x * kThreads + (threadIdx.x & ~63); x0 < S; x0 += step) {
+        const int64_t x = x0 + lane;
+        bool todo = x < S;
+        uint32_t b = 0;
+        if (todo) {
+            const K key = keys[x * M / S];  // S evenly spaced nonzeros
+            uint32_t r;
+            if constexpr (kTab > 0) r = (uint32_t)(compact_index(key, ltab) >> tab.coff[mode]) & tab.cmask[mode];
+            else r = extract_mode(key, tab, mode);
+            // Fibonacci hashing folds large modes onto nb buckets
+            b = hashed ? (uint32_t)(((uint64_t)(r * 2654435769u) * nb) >> 32) : r;
+        }
+        // lanes with the same bucket add once: a hot row would otherwise
+        // take one atomic per sampled nonzero on a single address
+        uint64_t left = __ballot(todo);
+        while (left) {
+            const int leader = __builtin_ctzll(left);
+            const uint32_t lb = (uint32_t)__shfl((int)b, leader);
+            const uint64_t same = __ballot(todo && b == lb);
+            if (lane == leader) atomicAdd(&cnt[lb], (uint32_t)__builtin_popcountll(same));
+            if (todo && b == lb) todo = false;
+            left &= ~same;
+        }
     }
 }
 
