@@ -558,6 +558,25 @@ int fill_mt_launch(const alto_tensor *t, const void *const *factors, int R, int 
         }
     }
     a.threads = a.dec.smask ? 1024 : atomic_threads(t->part->L);
+    if (!a.dec.smask && env_long("ALTO_MT_THREADS", 0) == 0) {
+        // LDS per workgroup: the flush queues (two rows per lane group) and,
+        // unless the keys are compact words, the byte tables (48 KB for a
+        // 95-bit index).  Small workgroups with large tables leave a compute
+        // unit few waves (two 256-thread workgroups: 8), so the workgroup
+        // grows until LDS admits at least 16 waves per compute unit.
+        const bool spec = R == 8 || R == 16 || R == 32 || R == 64;
+        const int vec = prec == ALTO_PREC_BF16 ? 8 : 4;
+        const uint64_t per_wave = spec ? 2ull * (64 / (R / vec)) * (R + 1) * 4 : 0;
+        const uint64_t table = a.dec.compact ? 0
+                               : t->key_bits <= 64 ? (uint64_t)(t->key_bits / 8) * 256 * (t->key_bits / 8)
+                                                   : (uint64_t)t->tab.tbytes128 * 256 * 16;
+        while (a.threads < 1024) {
+            const uint64_t lds = (uint64_t)(a.threads / 64) * per_wave + table;
+            const uint64_t wgs = lds ? (160 * 1024) / lds : 32;
+            if (wgs * (uint64_t)(a.threads / 64) >= 16) break;
+            a.threads *= 2;
+        }
+    }
     return ALTO_OK;
 }
 
