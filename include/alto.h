@@ -254,7 +254,7 @@ int alto_select(const alto_tensor *t, int mode, int R, int prec, alto_exec *out)
 
 /*
  * alto_selector_load — install selector weights (host floats, layout:
- * header {F = 14, H, K, nL} then feature mean[F], feature scale[F], the
+ * header {F = 15, H, K, nL} then feature mean[F], feature scale[F], the
  * training range fmin[F], fmax[F], the nL candidate segment counts,
  * W1[H*F], b1[H], W2[H*H], b2[H], W3[K*H], b3[K], with K = S*nL outputs
  * (S = 2 or 3 strategies) = predicted log2 times of (atomic, L_0) ..
@@ -264,7 +264,7 @@ int alto_select(const alto_tensor *t, int mode, int R, int prec, alto_exec *out)
  */
 int alto_selector_load(const float *weights, size_t n);
 
-/* alto_selector_features — the F = 14 selector features of (tensor, mode,
+/* alto_selector_features — the F = 15 selector features of (tensor, mode,
  * R, prec), written to host `out`: log2 I_mode, log2 nnz, log2 nnz/I_mode,
  * N, log2 R, prec, B/32, key bits/64, log2 of the sum and of the largest of
  * the other dims, log2 bytes of the smallest other factor matrix,
@@ -272,7 +272,10 @@ int alto_selector_load(const float *weights, size_t n);
  * (and alto_append) from the row counts of S = min(nnz, 2^20) evenly spaced
  * nonzeros: log2(largest row count * I_mode / S) and log2(distinct rows in
  * the sample / min(S, I_mode)) (modes over 2^24 rows are counted in 2^24
- * hashed buckets).  Host only. */
+ * hashed buckets); last, log2(max(1, nnz / 65536)) when R is 8, 16, 32 or 64
+ * and the smallest other factor matrix takes at most 64 KB (the MTTKRP then
+ * gathers it from LDS while segments hold at least 65 536 nonzeros), else -1.
+ * Host only. */
 int alto_selector_features(const alto_tensor *t, int mode, int R, int prec, float *out);
 
 /*

@@ -326,7 +326,7 @@ class AltoTensor:
         return STRATEGY_NAME[ex.strategy], ex.num_segments
 
     def selector_features(self, mode: int, R: int, prec: str = "f32") -> np.ndarray:
-        f = np.zeros(14, np.float32)
+        f = np.zeros(15, np.float32)
         _check(self._lib.alto_selector_features(self._h, mode, R, PREC[prec], f.ctypes.data))
         return f
 

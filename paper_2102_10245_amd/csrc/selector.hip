@@ -17,7 +17,7 @@
 namespace alto {
 namespace {
 
-constexpr int kF = 14;
+constexpr int kF = 15;
 
 struct Selector {
     bool loaded = false;
@@ -53,6 +53,12 @@ void features(const alto_tensor *t, int mode, int R, int prec, float *f) {
     f[11] = (float)std::log2(I * R);
     f[12] = t->row_hot[mode];       // skew of the output mode
     f[13] = t->row_distinct[mode];
+    // The MTTKRP gathers the smallest other factor matrix from LDS when it
+    // takes at most 64 KB and segments hold at least 65 536 nonzeros (see
+    // fill_mt_launch): log2 of the largest segment count that still does, or
+    // -1 when the matrix does not fit.
+    const bool spec = R == 8 || R == 16 || R == 32 || R == 64;
+    f[14] = spec && min_other * R * fbytes <= 65536.0 ? (float)std::log2(std::max(1.0, M / 65536.0)) : -1.f;
 }
 
 const int kOrder[3] = {ALTO_STRATEGY_ATOMIC, ALTO_STRATEGY_STAGED, ALTO_STRATEGY_SORTED};
@@ -178,7 +184,7 @@ int alto_selector_load(const float *w, size_t n) {
     s.K = (int)w[2];
     s.nL = (int)w[3];
     if (s.F != kF || s.H < 1 || s.H > 256 || s.nL < 1 || (s.K != 2 * s.nL && s.K != 3 * s.nL))
-        return set_error(ALTO_E_INVAL, "selector header must be {14, H<=256, 2*nL or 3*nL, nL}");
+        return set_error(ALTO_E_INVAL, "selector header must be {15, H<=256, 2*nL or 3*nL, nL}");
     const size_t need = 4 + 4 * (size_t)s.F + s.nL + (size_t)s.H * s.F + s.H + (size_t)s.H * s.H + s.H +
                         (size_t)s.K * s.H + s.K;
     if (n != need) return set_error(ALTO_E_INVAL, "selector weight count does not match its header");

@@ -1,7 +1,7 @@
 """Timing corpus, training and evaluation of the MTTKRP execution selector.
 
 The selector is a perceptron with two hidden ReLU layers of 64 units.  From
-14 features of (tensor, mode, rank, precision) it predicts, for every
+15 features of (tensor, mode, rank, precision) it predicts, for every
 candidate execution (strategy in {atomic, staged, sorted} x segment count L),
 log2 of the MTTKRP time relative to the fastest candidate; the library runs
 the candidate with the smallest prediction.
@@ -42,7 +42,7 @@ if ROOT not in sys.path:
 STRATEGIES = ("atomic", "staged", "sorted")
 LS = (256, 512, 1024, 2048, 4096, 8192, 16384)
 K = len(STRATEGIES) * len(LS)
-F, H = 14, 64
+F, H = 15, 64
 N_TRAIN, N_TOTAL = 400, 500
 SEED = 20210245
 WEIGHTS = os.path.join(HERE, "selector_weights.f32")
