@@ -614,6 +614,17 @@ std::vector<EventPair> g_tm_pending, g_tm_free;
 struct CallTimer {
     EventPair ev{nullptr, nullptr};
     bool active = false;
+    CallTimer() = default;
+    CallTimer(const CallTimer &) = delete;
+    CallTimer &operator=(const CallTimer &) = delete;
+    // a call that failed between begin and end gives its pair back unrecorded
+    ~CallTimer() {
+        if (!ev.first) return;
+        if (active) {
+            std::lock_guard<std::mutex> lk(g_tm_mu);
+            g_tm_free.push_back(ev);
+        }
+    }
     int begin(hipStream_t s) {
         {
             std::lock_guard<std::mutex> lk(g_tm_mu);
@@ -625,16 +636,20 @@ struct CallTimer {
         }
         if (!ev.first) {
             ALTO_HIP(hipEventCreate(&ev.first));
-            ALTO_HIP(hipEventCreate(&ev.second));
+            if (hipEventCreate(&ev.second) != hipSuccess) {
+                (void)hipEventDestroy(ev.first);
+                ev.first = nullptr;
+                return set_error(ALTO_E_HIP, "hipEventCreate");
+            }
         }
+        active = true;  // from here the pair goes back to the pool on failure
         ALTO_HIP(hipEventRecord(ev.first, s));
-        active = true;
         return ALTO_OK;
     }
     int end(hipStream_t s) {
         if (!active) return ALTO_OK;
-        active = false;
         ALTO_HIP(hipEventRecord(ev.second, s));
+        active = false;
         std::lock_guard<std::mutex> lk(g_tm_mu);
         g_tm_pending.push_back(ev);
         return ALTO_OK;

@@ -178,6 +178,37 @@ def test_cp_als_tall_mode_matches_oracle(R, rows):
     t.close()
 
 
+@pytest.mark.parametrize("R", [8, 32, 64])
+def test_cp_als_ridge_retry_matches_oracle(R):
+    """Column 3 of the start is zero in modes 1 and 2, so every normal-equation
+    matrix of the sweeps has a zero row and column: each update takes the
+    ridge retry (1e-10 tr(V)/R on the diagonal), on the GPU (Gauss-Jordan,
+    pivot <= 0) as in the oracle (Cholesky).  Column 3 stays zero with
+    lambda 0; the other columns, fit and lambda match the oracle.  R = 8 and
+    32 solve in one wave, R = 64 in a workgroup over LDS."""
+    rec = synth.scaled(synth.WORKLOADS["uniform3_1000x800x600_100k"], 30_000)
+    coords, vals = synth.coo(rec)
+    c, v = to_dev(coords, vals)
+    t = alto.AltoTensor.build(c, v, rec.dims)
+    init = synth.factors(rec.seed + 3, rec.dims, R)
+    init[1][:, 3] = 0.0
+    init[2][:, 3] = 0.0
+    oA, olam, ofit = oracle.cp_als(rec.dims, coords, vals, init, 2)
+    fd = factors_dev(init)
+    lam, fit = t.cp_als(fd, 2)
+    lam = lam.cpu().numpy()
+    print("ridge R", R, "fit", fit, "oracle", ofit, "lambda_3", lam[3], olam[3], flush=True)
+    assert np.all(np.abs(fit - ofit) <= 1e-5)
+    assert olam[3] == 0.0 and lam[3] == 0.0
+    keep = np.arange(R) != 3
+    assert np.allclose(lam[keep], olam[keep], rtol=1e-3)
+    for f, a in zip(fd, oA):
+        f = f.cpu().numpy()
+        assert np.all(f[:, 3] == 0.0) and np.all(a[:, 3] == 0.0)
+        assert rel_fro(f, a) <= 1e-3
+    t.close()
+
+
 def test_cp_als_singular_normal_equations():
     # all-zero factors: every Gram is zero, so is the ridge, and the normal
     # equations stay singular -> ALTO_E_NOTSPD
