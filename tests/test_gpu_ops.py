@@ -76,7 +76,8 @@ APPEND_CASES = [
 def test_append_equals_build_of_concatenation(rec, nb, L):
     """Building from the first part and appending the rest, batch by batch,
     gives the tensor alto_build makes from the whole COO list, bit for bit:
-    index, values, norm, segments, intervals and coverage."""
+    index, values, norm, segments, intervals, coverage and the selector's
+    features."""
     import torch
     coords, vals = synth.coo(rec)
     M = coords.shape[1]
@@ -100,6 +101,8 @@ def test_append_equals_build_of_concatenation(rec, nb, L):
     assert torch.equal(gs, rs) and torch.equal(gl, rl)
     for n in range(len(rec.dims)):
         assert torch.equal(t.export_coverage(n), ref.export_coverage(n))
+        # the selector's features, the row-count ones included
+        assert np.array_equal(t.selector_features(n, 16, "f32"), ref.selector_features(n, 16, "f32"))
     # and the keys are the oracle's
     (olo, ohi), _, lay, _ = oracle_alto(rec.dims, coords, vals)
     glo, ghi = keys_numpy(gk, gi["key_bits"])
