@@ -369,12 +369,19 @@ def cpu_baseline(rec, coords, vals, init, R, N, seconds):
     oracle.build(force=False)
     init = [np.asarray(f, np.float64) for f in init]
 
-    def leg(fn, s0):
+    def timed(fn, s):
         t0 = time.perf_counter()
         for mode in range(N):
-            fn(rec.dims, coords[:, :s0], vals[:s0], init, mode)
-        dt = time.perf_counter() - t0
-        s = int(min(coords.shape[1], max(s0, s0 * seconds / max(dt, 1e-9))))
+            fn(rec.dims, coords[:, :s], vals[:s], init, mode)
+        return time.perf_counter() - t0
+
+    def leg(fn, s0):
+        # two probes separate the per-call cost (thread-private outputs of
+        # I_n x R doubles are cleared and added up) from the per-nonzero one
+        d0, d1 = timed(fn, s0), timed(fn, 4 * s0)
+        per_nnz = max((d1 - d0) / (3 * s0), 1e-12)
+        fixed = max(d0 - per_nnz * s0, 0.0)
+        s = int(min(coords.shape[1], max(4 * s0, (seconds - fixed) / per_nnz)))
         used = 1
         t0 = time.perf_counter()
         for mode in range(N):
