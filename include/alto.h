@@ -185,8 +185,11 @@ int alto_partition(alto_tensor *t, int num_segments, hipStream_t stream);
  *            partition into that many segments becomes the current one; it
  *            is built on first use (which synchronizes the stream) and kept,
  *            with up to three other recent partitions, for later calls.
- * Asynchronous otherwise.  FP32 accumulation; atomics make the summation
- * order, hence the last bits, run-dependent.
+ * Asynchronous otherwise.  Products and run sums in FP32; the strategies
+ * that take the nonzeros in linearized order (atomic, staged) add them
+ * into an FP64 accumulator that is rounded into out at the end, the
+ * segment-local order (sorted) adds one FP32 atomic per (segment, row) run.
+ * Atomics make the summation order, hence the last bits, run-dependent.
  */
 int alto_mttkrp(alto_tensor *t, const void *const *factors, int R, int prec, int mode,
                 float *out, const alto_exec *ex, hipStream_t stream);
